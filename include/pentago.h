@@ -1,0 +1,208 @@
+/*
+ * pentago.h -- C ABI of the MI355X (gfx950) pentago retrograde library.
+ *
+ * The library computes exact rotation-abstracted values of pentago positions
+ * (Irving, "Pentago is a First Player Win", arXiv:1404.0743):
+ *   - the n+1 -> n layer sweep over one section or many sections
+ *     (Section II recurrence, Section III rotation abstraction, Section IV
+ *     sections and 8^4 blocks),
+ *   - exact values of arbitrary boards solved to the full board (the serial
+ *     endgame solver of Section VIII, rotations handled by rmax only),
+ *   - a query server that answers boards from resident sections or by search.
+ *
+ * Conventions (fixed by this library; the paper leaves them open):
+ *   cell        6*r + c, r counted downward, c rightward
+ *   quadrant    2*(r/3) + c/3: 0 top-left, 1 top-right, 2 bottom-left, 3 bottom-right
+ *   local cell  3*(r%3) + c%3; a quadrant pattern is the ternary code
+ *               sum_l digit_l * 3^l with digit 0 empty, 1 black, 2 white
+ *   one turn    90 degrees counter-clockwise: local (lr, lc) moves to (2-lc, lr)
+ *   L = Z4^4    g = g0 + 4*g1 + 16*g2 + 64*g3, g_j counter-clockwise turns of quadrant j
+ *   side to move  black when the black and white counts are equal, white when
+ *               black has one more (Section II validity)
+ *
+ * Memory: every pointer named "device" is device memory of the current HIP
+ * device, allocated and owned by the caller; the library only borrows it for
+ * the call (or, for the server, until destroy).  Host pointers are read
+ * during the call only.  Calls that take a hip_stream are stream-ordered and
+ * asynchronous: they return after enqueueing, results are ready when the
+ * stream reaches them.  A NULL stream means the default stream.
+ *
+ * Errors: every function returns 0 on success or a negative PENTAGO_E* code.
+ * No C++ exception crosses this boundary.  pentago_strerror() names a code;
+ * pentago_last_error() gives the detail of the calling thread's last failure.
+ */
+#ifndef PENTAGO_H
+#define PENTAGO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PENTAGO_OK 0
+#define PENTAGO_EINVAL (-1)   /* bad counts, board, index, size or NULL argument */
+#define PENTAGO_ENOCHILD (-2) /* a child section table that is needed is NULL */
+#define PENTAGO_ENOMEM (-3)   /* the library could not allocate its own scratch */
+#define PENTAGO_ERANGE (-4)   /* a size beyond what the call supports */
+#define PENTAGO_EAGAIN (-5)   /* try again: queue full, or result not ready */
+#define PENTAGO_EDEVICE (-6)  /* a HIP runtime error; see pentago_last_error() */
+
+/* A set of elements of L: bit g lives in w[g >> 6] at position g & 63. */
+typedef struct {
+    uint64_t w[4];
+} pentago_set256;
+
+/* The rotation-abstracted value of one board b (Section III): for every g in
+ * L, win has bit g iff the side to move wins g.b, notlose has bit g iff it
+ * does not lose.  64 bytes.  Invariant: win is a subset of notlose. */
+typedef struct {
+    pentago_set256 win, notlose;
+} pentago_superinfo;
+
+/* A concrete board: the ternary code of each quadrant (0 .. 19682). */
+typedef struct {
+    uint16_t q[4];
+} pentago_board;
+
+/* A section (Section IV): the boards with black[j] black and white[j]
+ * white stones in quadrant j.  Valid iff black[j] + white[j] <= 9 for every j
+ * and sum(black) - sum(white) is 0 or 1. */
+typedef struct {
+    uint8_t black[4], white[4];
+} pentago_section;
+
+/* ---------------------------------------------------------------- layout */
+
+/* Shape of a section: shape[j] is the number of rotation-minimal patterns of
+ * quadrant j's (black, white) class (Section IV, Fig. 4), entries their
+ * product (number of superinfos), positions the number of boards
+ * prod_j 9!/(b_j! w_j! (9-b_j-w_j)!).  Any output pointer may be NULL. */
+int pentago_section_shape(pentago_section s, uint32_t shape[4], uint64_t *entries,
+                          uint64_t *positions);
+
+/* Offset (in superinfos) of entry idx in the section's table.  The table is
+ * tiled in blocks of 8x8x8x8 entries (Section IV), smaller where a dimension
+ * ends; blocks are stored in row-major order of block coordinates (dimension
+ * 3 fastest), and the entries of a block row-major over its own extents. */
+int pentago_section_offset(pentago_section s, const uint32_t idx[4], uint64_t *offset);
+
+/* Board of entry idx: quadrant j holds the idx[j]-th rotation-minimal pattern
+ * of its class, patterns ordered by increasing ternary code. */
+int pentago_section_board(pentago_section s, const uint32_t idx[4], pentago_board *board);
+
+/* The section whose table child[j] of pentago_solve_section must hold: s with
+ * the side to move's count in quadrant j raised by one (Section IV: a stone
+ * placed in quadrant j changes only that quadrant's index).  EINVAL if
+ * quadrant j is full. */
+int pentago_child_section(pentago_section s, int j, pentago_section *child);
+
+/* ---------------------------------------------------------------- sweep */
+
+/* The n+1 -> n sweep of one section (Section II recurrence on Section III
+ * tables, Section IV data layout, Fig. 3 line structure).
+ *   child[j]  device table of pentago_child_section(s, j) (entries x 64 B, in
+ *             the blocked layout), or NULL when quadrant j is full.  When s
+ *             has 35 stones its children are full boards: a NULL child[j] then
+ *             selects on-demand evaluation of those boards.
+ *   out       device, entries x 64 B, written completely.
+ * Sections with 36 stones (no empty cell) are evaluated directly (f_c - f_cbar,
+ * Section II).  out must not overlap any child table.  EINVAL for an invalid
+ * section or NULL out; ENOCHILD for a missing child that is needed. */
+int pentago_solve_section(pentago_section s, const pentago_superinfo *const child[4],
+                          pentago_superinfo *out, void *hip_stream);
+
+/* One section of a batch: its counts, its four child tables as for
+ * pentago_solve_section, and its output. */
+typedef struct {
+    pentago_section section;
+    const pentago_superinfo *child[4];
+    pentago_superinfo *out;
+} pentago_section_job;
+
+/* Many sections of one slice (all the same stone count) in one persistent
+ * launch, work-balanced across the GPU by a device work queue.  Results are
+ * bit-identical to calling pentago_solve_section on each job.  Jobs must not
+ * write to any table another job of the same call reads.  n <= 65536. */
+int pentago_solve_sections(const pentago_section_job *jobs, size_t n, void *hip_stream);
+
+/* ---------------------------------------------------------------- endgame */
+
+/* Exact superinfo of n arbitrary boards, each solved to the full board over
+ * all 256 quadrant rotations (the serial endgame solver of Section VIII: the
+ * descendants of a board under placements only, rotations folded in by
+ * rmax).  The side to move comes from the counts; boards that already show
+ * five in a row are valid (those rotations are terminal).
+ *   boards  device, n boards
+ *   out     device, n x 64 B
+ *   status  device int32 or NULL: incremented once per invalid board (a
+ *           quadrant code >= 19683, counts that are not a valid position, or
+ *           more than 10 empty cells); such a board's output is all zero.
+ * Boards may have different numbers of empty cells: the library bins them on
+ * the device (most empty cells first) and solves all of them in one
+ * persistent launch fed by a device work queue.  ERANGE for n > 2^30. */
+int pentago_eval_batch(const pentago_board *boards, size_t n, pentago_superinfo *out,
+                       int32_t *status, void *hip_stream);
+
+/* The plain form of pentago_eval_batch: one launch per group of boards with
+ * the same number of empty cells, one workgroup per board.  Same results.
+ * Synchronises the stream once, to read the group sizes. */
+int pentago_eval_batch_grouped(const pentago_board *boards, size_t n, pentago_superinfo *out,
+                               int32_t *status, void *hip_stream);
+
+/* ---------------------------------------------------------------- serving */
+
+typedef struct pentago_server pentago_server;
+
+typedef struct {
+    uint64_t memory_budget;  /* bytes of device scratch the server may hold for searches */
+    uint32_t max_inflight;   /* queries admitted but not yet polled */
+    uint32_t max_batch;      /* queries per device batch */
+    uint32_t streams;        /* HIP streams the server launches on (1..8) */
+} pentago_serve_config;
+
+typedef struct {
+    uint64_t queries;        /* answered so far */
+    uint64_t lookups;        /* answered from a resident section */
+    uint64_t searches;       /* answered by on-device search */
+    uint64_t batches;        /* device batches launched */
+    double p50_us, p99_us;   /* latency from submit to result visible on the host */
+    double queries_per_s;    /* answered queries over the time since the first submit */
+} pentago_serve_stats;
+
+/* Create a server on the current device.  A background thread batches
+ * submitted queries by kind and empties count and admits them while
+ * in-flight slots and scratch memory allow (continuous batching). */
+int pentago_serve_create(const pentago_serve_config *cfg, pentago_server **out);
+
+/* Register a resident solved section (device table, borrowed until destroy).
+ * Queries whose quadrant counts match a resident section are answered by
+ * lookup (Section VIII: positions inside the database are read, not solved). */
+int pentago_serve_add_section(pentago_server *srv, pentago_section s,
+                              const pentago_superinfo *table);
+
+/* Submit one board.  EAGAIN when max_inflight queries are pending; EINVAL
+ * for an invalid board; ERANGE for more than 10 empty cells on a board that
+ * no resident section holds. */
+int pentago_serve_submit(pentago_server *srv, pentago_board board, uint64_t *ticket);
+
+/* Fetch the result of a ticket into host memory.  EAGAIN while pending;
+ * EINVAL for an unknown (or already fetched) ticket. */
+int pentago_serve_poll(pentago_server *srv, uint64_t ticket, pentago_superinfo *out);
+
+int pentago_serve_stats_get(pentago_server *srv, pentago_serve_stats *stats);
+
+/* Stop the server thread, wait for the device, release everything. */
+int pentago_serve_destroy(pentago_server *srv);
+
+/* ---------------------------------------------------------------- misc */
+
+const char *pentago_strerror(int code);
+const char *pentago_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,40 @@
+/*
+ * pentago_debug.h -- host-side self-check entry points of the library.
+ *
+ * These run the library's own rotation-abstracted primitives (the same
+ * source the GPU kernels are compiled from) on the host CPU, so that they can
+ * be checked against their definitions without a GPU.  Sets use the layout
+ * of pentago_set256 (bit g of L in word g >> 6 at position g & 63).
+ */
+#ifndef PENTAGO_DEBUG_H
+#define PENTAGO_DEBUG_H
+
+#include <stdint.h>
+
+#include "pentago.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* The set of g in L for which g.board has five in a row of colour (1 black,
+ * 2 white) (Section III). */
+int pentago_debug_five(pentago_board board, int color, pentago_set256 *out);
+
+/* rmax(in)(g) = OR over the 8 single-quadrant turns r of in(g + r) (Section III). */
+int pentago_debug_rmax(const pentago_set256 *in, pentago_set256 *out);
+
+/* out(g) = in(g - k e_d): the table of a board whose quadrant d is turned k
+ * more times counter-clockwise (Section III, f_b -> f_gb for g in L). */
+int pentago_debug_shift(const pentago_set256 *in, int d, int k, pentago_set256 *out);
+
+/* Rotation-minimal pattern of a quadrant code: its index in its (black,
+ * white) class and the least number of counter-clockwise turns k taking the
+ * code to it (Section IV). */
+int pentago_debug_canon(int code, int *index, int *k);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -33,7 +33,7 @@ def build(force=False):
     """Compile the oracle with gcc (always recompiles when force is set)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-march=native", "-std=c99", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
                                "-pthread", "-Wall", "-Wno-unused-function", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB

@@ -1,0 +1,62 @@
+// debug.hip -- host-side self-check entry points (include/pentago_debug.h).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "../../include/pentago_debug.h"
+#include "internal.h"
+
+using namespace pg;
+
+static Set256 from_abi(const pentago_set256 *s)
+{
+    Set256 r;
+    memcpy(r.w, s->w, 32);
+    return r;
+}
+
+static void to_abi(const Set256 &s, pentago_set256 *out) { memcpy(out->w, s.w, 32); }
+
+extern "C" {
+
+int pentago_debug_five(pentago_board board, int color, pentago_set256 *out)
+{
+    if (!out || (color != 1 && color != 2)) return fail(PENTAGO_EINVAL, "invalid arguments");
+    const HostTables &H = host_tables();
+    LineMasks lm[4];
+    for (int j = 0; j < 4; j++) {
+        if (board.q[j] >= 19683) return fail(PENTAGO_EINVAL, "invalid quadrant code");
+        unsigned m = 0;
+        int x = board.q[j];
+        for (int l = 0; l < 9; l++, x /= 3)
+            if (x % 3 == color) m |= 1u << l;
+        lm[j] = H.lm[j * 512 + m];
+    }
+    to_abi(five_set(lm[0], lm[1], lm[2], lm[3]), out);
+    return 0;
+}
+
+int pentago_debug_rmax(const pentago_set256 *in, pentago_set256 *out)
+{
+    if (!in || !out) return fail(PENTAGO_EINVAL, "NULL argument");
+    to_abi(rmax(from_abi(in)), out);
+    return 0;
+}
+
+int pentago_debug_shift(const pentago_set256 *in, int d, int k, pentago_set256 *out)
+{
+    if (!in || !out || d < 0 || d > 3) return fail(PENTAGO_EINVAL, "invalid arguments");
+    to_abi(shift_dim(from_abi(in), d, k), out);
+    return 0;
+}
+
+int pentago_debug_canon(int code, int *index, int *k)
+{
+    if (code < 0 || code >= 19683 || !index || !k) return fail(PENTAGO_EINVAL, "invalid arguments");
+    const uint16_t c = host_tables().canon[code];
+    *index = c & 0xfff;
+    *k = c >> 12;
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// eval.hip -- C ABI of the endgame solver: arbitrary boards solved to the
+// full board over all 256 quadrant rotations (Section VIII serial solver),
+// binned by number of empty cells on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <set>
+
+#include "internal.h"
+
+namespace pg {
+
+static std::mutex g_pool_mutex;
+static std::set<int> g_pool_ready;
+
+// Keep stream-ordered allocations pooled instead of returning them to the
+// driver after every call.
+void keep_pool(int dev)
+{
+    std::lock_guard<std::mutex> lock(g_pool_mutex);
+    if (g_pool_ready.count(dev)) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t big = ~0ull;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &big);
+    }
+    g_pool_ready.insert(dev);
+}
+
+int eval_grid(int *grid)
+{
+    static int cached[64] = {0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 64 && cached[dev]) {
+        *grid = cached[dev];
+        return 0;
+    }
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    // two 256-thread workgroups per CU fit the LDS of the deepest in-LDS DAG
+    *grid = std::max(1, 2 * cus);
+    if (dev < 64) cached[dev] = *grid;
+    keep_pool(dev);
+    return 0;
+}
+
+struct EvalAlloc {
+    void *base = nullptr;
+    EvalScratch S;
+};
+
+static int eval_alloc(size_t n, int grid, hipStream_t st, EvalAlloc *A)
+{
+    const size_t ints = 64;
+    const size_t glayer = (size_t)grid * 2 * kDagGlobalLayer * 64;
+    const size_t bytes = glayer + ints * 4 + 8 + n * 4 + n + 256;
+    hipError_t e = hipMallocAsync(&A->base, bytes, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(eval scratch)");
+    char *p = (char *)A->base;
+    A->S.global_layers = (uint4 *)p;
+    p += glayer;
+    A->S.count = (int *)p;
+    A->S.start = A->S.count + 16;
+    A->S.cursor = A->S.count + 32;
+    p += ints * 4;
+    A->S.counter = (unsigned long long *)p;
+    p += 8;
+    A->S.order = (int *)p;
+    p += n * 4;
+    A->S.empties = (uint8_t *)p;
+    A->S.global_slots = grid;
+    return 0;
+}
+
+}  // namespace pg
+
+using namespace pg;
+
+extern "C" {
+
+int pentago_eval_batch(const pentago_board *boards, size_t n, pentago_superinfo *out,
+                       int32_t *status, void *hip_stream)
+{
+    if (n && (!boards || !out)) return fail(PENTAGO_EINVAL, "NULL boards or out");
+    if (n > (size_t)1 << 30) return fail(PENTAGO_ERANGE, "more than 2^30 boards");
+    if (n == 0) return 0;
+    DevTables T;
+    int rc = device_tables(&T);
+    if (rc) return rc;
+    int grid;
+    rc = eval_grid(&grid);
+    if (rc) return rc;
+    const hipStream_t st = (hipStream_t)hip_stream;
+    EvalAlloc A;
+    rc = eval_alloc(n, grid, st, &A);
+    if (rc) return rc;
+    hipError_t e = launch_eval_bin((const uint64_t *)boards, n, A.S, status, (uint4 *)out, T, st);
+    if (e == hipSuccess)
+        e = launch_eval_persistent((const uint64_t *)boards, n, (uint4 *)out, A.S, grid, T, st);
+    (void)hipFreeAsync(A.base, st);
+    if (e != hipSuccess) return hip_fail(e, "eval launch");
+    return 0;
+}
+
+int pentago_eval_batch_grouped(const pentago_board *boards, size_t n, pentago_superinfo *out,
+                               int32_t *status, void *hip_stream)
+{
+    if (n && (!boards || !out)) return fail(PENTAGO_EINVAL, "NULL boards or out");
+    if (n > (size_t)1 << 30) return fail(PENTAGO_ERANGE, "more than 2^30 boards");
+    if (n == 0) return 0;
+    DevTables T;
+    int rc = device_tables(&T);
+    if (rc) return rc;
+    int grid;
+    rc = eval_grid(&grid);
+    if (rc) return rc;
+    const hipStream_t st = (hipStream_t)hip_stream;
+    EvalAlloc A;
+    rc = eval_alloc(n, grid, st, &A);
+    if (rc) return rc;
+    hipError_t e = launch_eval_bin((const uint64_t *)boards, n, A.S, status, (uint4 *)out, T, st);
+    int start[16];
+    if (e == hipSuccess) e = hipMemcpyAsync(start, A.S.start, sizeof(start), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    for (int k = 10; k >= 0 && e == hipSuccess; k--) {
+        const int first = start[k];
+        const int count = (k == 0 ? start[11] : start[k - 1]) - first;
+        e = launch_eval_group((const uint64_t *)boards, k, first, count, (uint4 *)out, A.S, T, st);
+    }
+    (void)hipFreeAsync(A.base, st);
+    if (e != hipSuccess) return hip_fail(e, "eval launch");
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,26 @@
+// internal.h -- helpers shared by the C ABI implementation files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/pentago.h"
+#include "kernels.h"
+
+namespace pg {
+
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *where);
+int device_tables(DevTables *out);
+
+bool section_valid(const pentago_section &s);
+int section_mover(const pentago_section &s);
+int section_stones(const pentago_section &s);
+pentago_section child_of(const pentago_section &s, int j);
+void section_shape_of(const pentago_section &s, int m[4]);
+uint64_t host_block_offset(const int *m, const int *idx);
+int make_job(const pentago_section &s, const pentago_superinfo *const child[4],
+             pentago_superinfo *out, SweepJob *J, int force_d, int forceG);
+size_t prep_bytes(const SweepJob &J, int j);
+
+}  // namespace pg

@@ -1,0 +1,82 @@
+// kernels.h -- device-side job descriptions shared by the kernels and the
+// host launch code.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "set256.h"
+#include "tables.h"
+
+namespace pg {
+
+// Read-only tables in device memory (one copy per device).
+struct DevTables {
+    const uint16_t *canon;   // [19683] index in class | k << 12
+    const QInfo *qinfo;      // [4995]
+    const LineMasks *lm;     // [4 * 512]
+    const uint32_t *dag_node;   // all DAG layouts back to back (cmask | omask << 16)
+    const uint16_t *dag_rank;   // all rank tables back to back
+    int dag_node_off[11];       // start of layout e in dag_node
+    int dag_rank_off[11];       // start of layout e in dag_rank
+    int dag_layer[11][12];      // layer starts (relative) of layout e
+    int dag_max[11];            // largest layer of layout e
+};
+
+// One section sweep (Section IV): a parent section, its child sections and
+// the tiling of its entries into lines along dimension d (Fig. 3: a line of
+// a parent depends on one line of the child section along the same dimension).
+struct SweepJob {
+    int m[4];          // parent shape
+    int qb[4];         // first QInfo index of each parent quadrant class
+    int cm[4];         // child extent along dimension j (0: quadrant j full)
+    int cqb[4];        // first QInfo index of the child class of quadrant j
+    const uint4 *child[4];
+    const uint4 *prep[4];   // prepared child terms of dimensions not staged (read)
+    uint4 *prep_out[4];     // where prep_kernel writes them (same buffers)
+    uint4 *out;
+    int mover;         // 1 black, 2 white
+    int d;             // dimension whose child lines are staged in LDS
+    int emask;         // dimensions whose quadrant has empty cells
+    int odmask;        // dimensions whose children are full boards evaluated on demand
+    int e;             // dimension that groups G lines into a tile (3, or 2 when d == 3)
+    int G;             // lines per tile
+    int ngroups;       // ceil(m[e] / G)
+    int o1, o2;        // the remaining two dimensions
+    long long ntiles;
+    int lds_bytes;     // dynamic LDS needed by one tile
+};
+
+// Host launchers (kernels.hip).
+hipError_t launch_sweep(const SweepJob &job, const DevTables &T, hipStream_t s);
+// Prepare the A/B child terms of dimension j (j in emask, j != d).
+hipError_t launch_prep(const SweepJob &job, int j, const DevTables &T, hipStream_t s);
+hipError_t launch_sweep_batch(const SweepJob *dev_jobs, const long long *dev_tile_start, int njobs,
+                              long long total_tiles, int lds_bytes, unsigned long long *dev_counter,
+                              int grid, const DevTables &T, hipStream_t s);
+
+// Endgame (Section VIII serial solver, one DAG per root).
+struct EvalScratch {
+    int *count;          // [16]: per empties count 0..10, [11] invalid
+    int *start;          // [16]
+    int *cursor;         // [16]
+    int *order;          // [n] roots sorted by empties, most first
+    uint8_t *empties;    // [n]
+    unsigned long long *counter;  // work counter of the persistent launch
+    uint4 *global_layers;         // DAG layers for roots with 9-10 empties
+    int global_slots;             // number of roots the global layer buffer holds at once
+};
+
+hipError_t launch_eval_bin(const uint64_t *boards, size_t n, const EvalScratch &S, int *status,
+                           uint4 *out, const DevTables &T, hipStream_t s);
+hipError_t launch_eval_persistent(const uint64_t *boards, size_t n, uint4 *out,
+                                  const EvalScratch &S, int grid, const DevTables &T,
+                                  hipStream_t s);
+hipError_t launch_eval_group(const uint64_t *boards, int e, int first, int count, uint4 *out,
+                             const EvalScratch &S, const DevTables &T, hipStream_t s);
+
+int dag_lds_bytes(int e);
+
+// Nodes of the largest layer of any supported root (10 empty cells).
+constexpr int kDagGlobalLayer = 4200;
+
+}  // namespace pg

@@ -1,0 +1,670 @@
+// kernels.hip -- HIP kernels for gfx950: the section sweep (Sections II-IV)
+// and the endgame DAG solver (Section VIII).
+//
+// Data layout in HBM: a section table is entries x 64 B superinfos (win
+// words then not-lose words) in the 8^4-blocked order of Section IV.  One
+// lane owns one entry and keeps each 256-bit set in eight VGPRs, so every
+// set operation is plain per-lane integer work; nothing here is a dense
+// contraction, so there is no MFMA.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace pg {
+
+__constant__ uint32_t c_pow3[10] = {1, 3, 9, 27, 81, 243, 729, 2187, 6561, 19683};
+
+__device__ __forceinline__ uint64_t block_offset(const int *m, const int *idx)
+{
+    int B[4], r[4], s[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        B[j] = idx[j] >> 3;
+        r[j] = idx[j] & 7;
+        s[j] = min(8, m[j] - 8 * B[j]);
+    }
+    const uint64_t m23 = (uint64_t)(m[2] * m[3]);
+    uint64_t off = (uint64_t)(8 * B[0]) * (uint64_t)m[1] * m23;
+    off += (uint64_t)(s[0] * 8 * B[1]) * m23;
+    off += (uint64_t)(s[0] * s[1] * 8 * B[2]) * (uint64_t)m[3];
+    off += (uint64_t)(s[0] * s[1] * s[2] * 8 * B[3]);
+    off += (uint64_t)(((r[0] * s[1] + r[1]) * s[2] + r[2]) * s[3] + r[3]);
+    return off;
+}
+
+__device__ __forceinline__ void load_info(const uint4 *p, Set256 &W, Set256 &N)
+{
+    const uint4 a = p[0], b = p[1], c = p[2], d = p[3];
+    W.w[0] = a.x; W.w[1] = a.y; W.w[2] = a.z; W.w[3] = a.w;
+    W.w[4] = b.x; W.w[5] = b.y; W.w[6] = b.z; W.w[7] = b.w;
+    N.w[0] = c.x; N.w[1] = c.y; N.w[2] = c.z; N.w[3] = c.w;
+    N.w[4] = d.x; N.w[5] = d.y; N.w[6] = d.z; N.w[7] = d.w;
+}
+
+__device__ __forceinline__ void store_info(uint4 *p, const Set256 &W, const Set256 &N)
+{
+    p[0] = make_uint4(W.w[0], W.w[1], W.w[2], W.w[3]);
+    p[1] = make_uint4(W.w[4], W.w[5], W.w[6], W.w[7]);
+    p[2] = make_uint4(N.w[0], N.w[1], N.w[2], N.w[3]);
+    p[3] = make_uint4(N.w[4], N.w[5], N.w[6], N.w[7]);
+}
+
+__device__ __forceinline__ Set256 board_five(const DevTables &T, const unsigned xm[4])
+{
+    const LineMasks l0 = T.lm[0 * 512 + xm[0]];
+    const LineMasks l1 = T.lm[1 * 512 + xm[1]];
+    const LineMasks l2 = T.lm[2 * 512 + xm[2]];
+    const LineMasks l3 = T.lm[3 * 512 + xm[3]];
+    return five_set(l0, l1, l2, l3);
+}
+
+// ---------------------------------------------------------------------------
+// Section sweep
+// ---------------------------------------------------------------------------
+
+// Index helpers: runtime dimension numbers only ever select among the four
+// registers (never index a local array, which would go to scratch).
+struct Idx4 {
+    int v[4];
+};
+
+__device__ __forceinline__ int get4(const Idx4 &x, int j)
+{
+    return j == 0 ? x.v[0] : j == 1 ? x.v[1] : j == 2 ? x.v[2] : x.v[3];
+}
+
+__device__ __forceinline__ void set4(Idx4 &x, int j, int val)
+{
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+        if (i == j) x.v[i] = val;
+}
+
+__device__ __forceinline__ int mdim(const SweepJob &J, int j)
+{
+    return j == 0 ? J.m[0] : j == 1 ? J.m[1] : j == 2 ? J.m[2] : J.m[3];
+}
+
+// A child entry's contribution, prepared once per child entry of a staged
+// line and used by every parent of the line that reaches it (Section III:
+// rmax is translation invariant, so it commutes with the canonicalising
+// shift; the immediate-win set of the placement is the child's own five-set
+// of the parent's colour, shifted the same way).
+//   A = F_c(child) | rmax(not N_child),  B = F_c(child) | rmax(not W_child)
+// JD is the child's dimension (the quadrant that received the stone).
+template <int JD>
+__device__ __forceinline__ void child_entry_terms(const SweepJob &J, const DevTables &T,
+                                                  const Idx4 &idx, Set256 &A, Set256 &B)
+{
+    const int c = J.mover;
+    unsigned cm_[4], om_[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const QInfo q = T.qinfo[(j == JD ? J.cqb[j] : J.qb[j]) + idx.v[j]];
+        cm_[j] = c == 1 ? q.bm : q.wm;
+        om_[j] = c == 1 ? q.wm : q.bm;
+    }
+    Set256 W, N;
+    if ((J.odmask >> JD) & 1) {
+        // a full board with the other side to move: value f_o - f_c (Section II)
+        const Set256 Fc = board_five(T, cm_);
+        const Set256 Fo = board_five(T, om_);
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            W.w[i] = Fo.w[i] & ~Fc.w[i];
+            N.w[i] = Fo.w[i] | ~Fc.w[i];
+        }
+    } else {
+        int cshape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
+        cshape[JD] = J.cm[JD];
+        load_info(J.child[JD] + 4 * block_offset(cshape, idx.v), W, N);
+    }
+    const Set256 Fc = board_five(T, cm_);
+    child_terms(Fc, W, N, A, B);
+}
+
+__device__ __forceinline__ Set256 lds_set(const uint4 *p)
+{
+    Set256 x;
+    const uint4 u = p[0], v = p[1];
+    x.w[0] = u.x; x.w[1] = u.y; x.w[2] = u.z; x.w[3] = u.w;
+    x.w[4] = v.x; x.w[5] = v.y; x.w[6] = v.z; x.w[7] = v.w;
+    return x;
+}
+
+// Children of one parent along a dimension JD that is not staged: their
+// A/B terms were prepared per child entry by prep_kernel (64 B each, in the
+// child section's blocked layout).
+template <int JD>
+__device__ __forceinline__ void direct_children(const SweepJob &J, const DevTables &T,
+                                                const Idx4 &idx, const QInfo &q, Set256 &Wnt,
+                                                Set256 &Nnt)
+{
+    int cshape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
+    cshape[JD] = J.cm[JD];
+    unsigned empt = ~(unsigned)(q.bm | q.wm) & 0x1ffu;
+    while (empt) {
+        const int cell = __builtin_ctz(empt);
+        empt &= empt - 1;
+        const uint16_t cc = T.canon[q.code + J.mover * c_pow3[cell]];
+        Idx4 cidx = idx;
+        cidx.v[JD] = cc & 0xfff;
+        const uint4 *p = J.prep[JD] + 4 * block_offset(cshape, cidx.v);
+        s_or_into(Wnt, shift_dim(lds_set(p), JD, cc >> 12));
+        s_or_into(Nnt, shift_dim(lds_set(p + 2), JD, cc >> 12));
+    }
+}
+
+// A/B terms of every entry of the child section along JD (for dimensions
+// that a sweep does not stage in LDS).
+template <int JD>
+__global__ void __launch_bounds__(256) prep_kernel(SweepJob J, DevTables T)
+{
+    int cshape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
+    cshape[JD] = J.cm[JD];
+    const long long n = (long long)cshape[0] * cshape[1] * cshape[2] * cshape[3];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        Idx4 idx;
+        long long r = i;
+        idx.v[3] = (int)(r % cshape[3]); r /= cshape[3];
+        idx.v[2] = (int)(r % cshape[2]); r /= cshape[2];
+        idx.v[1] = (int)(r % cshape[1]); r /= cshape[1];
+        idx.v[0] = (int)r;
+        Set256 A, B;
+        child_entry_terms<JD>(J, T, idx, A, B);
+        uint4 *p = J.prep_out[JD] + 4 * block_offset(cshape, idx.v);
+        p[0] = make_uint4(A.w[0], A.w[1], A.w[2], A.w[3]);
+        p[1] = make_uint4(A.w[4], A.w[5], A.w[6], A.w[7]);
+        p[2] = make_uint4(B.w[0], B.w[1], B.w[2], B.w[3]);
+        p[3] = make_uint4(B.w[4], B.w[5], B.w[6], B.w[7]);
+    }
+}
+
+template <int D>
+__device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile, uint4 *lds)
+{
+    const int grp = (int)(tile % J.ngroups);
+    const long long rest = tile / J.ngroups;
+    const int mo2 = mdim(J, J.o2);
+    Idx4 base;
+    base.v[0] = base.v[1] = base.v[2] = base.v[3] = 0;
+    set4(base, J.o2, (int)(rest % mo2));
+    set4(base, J.o1, (int)(rest / mo2));
+    set4(base, J.e, grp * J.G);
+    const int me = mdim(J, J.e);
+    const int nlines = min(J.G, me - grp * J.G);
+    const int c = J.mover;
+    const bool staged = (J.emask >> D) & 1;
+    const int cmD = J.cm[D];
+
+    // Phase 1: stage the child line(s) of dimension D (Fig. 3 "gather").
+    if (staged) {
+        const int total = nlines * cmD;
+        for (int it = threadIdx.x; it < total; it += blockDim.x) {
+            int v, ic;
+            if (D == 3) {
+                const int B3 = it / (8 * nlines);
+                const int rem = it - B3 * 8 * nlines;
+                const int s3 = min(8, cmD - 8 * B3);
+                v = rem / s3;
+                ic = 8 * B3 + rem % s3;
+            } else {
+                v = it % nlines;
+                ic = it / nlines;
+            }
+            Idx4 idx = base;
+            set4(idx, J.e, get4(base, J.e) + v);
+            idx.v[D] = ic;
+            Set256 A, B;
+            child_entry_terms<D>(J, T, idx, A, B);
+            uint4 *p = lds + 4 * (v * cmD + ic);
+            p[0] = make_uint4(A.w[0], A.w[1], A.w[2], A.w[3]);
+            p[1] = make_uint4(A.w[4], A.w[5], A.w[6], A.w[7]);
+            p[2] = make_uint4(B.w[0], B.w[1], B.w[2], B.w[3]);
+            p[3] = make_uint4(B.w[4], B.w[5], B.w[6], B.w[7]);
+        }
+        __syncthreads();
+    }
+
+    // Phase 2: every parent entry of the tile (Fig. 3 "compute").
+    const int mD = J.m[D];
+    const int total = nlines * mD;
+    for (int it = threadIdx.x; it < total; it += blockDim.x) {
+        int v, iD;
+        if (D == 3) {
+            // memory order inside a block: line (r2) slower, r3 faster
+            const int B3 = it / (8 * nlines);
+            const int rem = it - B3 * 8 * nlines;
+            const int s3 = min(8, mD - 8 * B3);
+            v = rem / s3;
+            iD = 8 * B3 + rem % s3;
+        } else {
+            v = it % nlines;
+            iD = it / nlines;
+        }
+        Idx4 idx = base;
+        set4(idx, J.e, get4(base, J.e) + v);
+        idx.v[D] = iD;
+
+        QInfo q[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) q[j] = T.qinfo[J.qb[j] + idx.v[j]];
+
+        Set256 Wnt = s_zero(), Nnt = s_zero();
+        if (J.emask == 0) Nnt = s_full();
+        if (staged) {
+            unsigned empt = ~(unsigned)(q[D].bm | q[D].wm) & 0x1ffu;
+            const uint4 *line = lds + 4 * (v * cmD);
+            while (empt) {
+                const int cell = __builtin_ctz(empt);
+                empt &= empt - 1;
+                const uint16_t cc = T.canon[q[D].code + c * c_pow3[cell]];
+                const int ic = cc & 0xfff, k = cc >> 12;
+                const uint4 *p = line + 4 * ic;
+                s_or_into(Wnt, shift_dim(lds_set(p), D, k));
+                s_or_into(Nnt, shift_dim(lds_set(p + 2), D, k));
+            }
+        }
+        // Children along the other dimensions with empty cells.
+        if (D != 0 && (J.emask & 1)) direct_children<0>(J, T, idx, q[0], Wnt, Nnt);
+        if (D != 1 && (J.emask & 2)) direct_children<1>(J, T, idx, q[1], Wnt, Nnt);
+        if (D != 2 && (J.emask & 4)) direct_children<2>(J, T, idx, q[2], Wnt, Nnt);
+        if (D != 3 && (J.emask & 8)) direct_children<3>(J, T, idx, q[3], Wnt, Nnt);
+
+        unsigned cm_[4], om_[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            cm_[j] = c == 1 ? q[j].bm : q[j].wm;
+            om_[j] = c == 1 ? q[j].wm : q[j].bm;
+        }
+        const Set256 Fc = board_five(T, cm_);
+        const Set256 Fo = board_five(T, om_);
+        Set256 W, N;
+        combine(Fc, Fo, Wnt, Nnt, W, N);
+        store_info(J.out + 4 * block_offset(J.m, idx.v), W, N);
+    }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) sweep_kernel(SweepJob J, DevTables T)
+{
+    extern __shared__ uint4 lds[];
+    sweep_tile<D>(J, T, blockIdx.x, lds);
+}
+
+// Many sections in one persistent launch: workgroups take tiles from a
+// device counter; tile_start[j] is the first global tile of job j.
+__global__ void __launch_bounds__(256)
+    sweep_batch_kernel(const SweepJob *jobs, const long long *tile_start, int njobs,
+                       long long total, unsigned long long *counter, DevTables T)
+{
+    extern __shared__ uint4 lds[];
+    __shared__ long long s_tile;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (long long)atomicAdd(counter, 1ull);
+        __syncthreads();
+        const long long t = s_tile;
+        __syncthreads();
+        if (t >= total) break;
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tile_start[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const SweepJob &J = jobs[lo];
+        const long long local = t - tile_start[lo];
+        switch (J.d) {
+        case 0: sweep_tile<0>(J, T, local, lds); break;
+        case 1: sweep_tile<1>(J, T, local, lds); break;
+        case 2: sweep_tile<2>(J, T, local, lds); break;
+        default: sweep_tile<3>(J, T, local, lds); break;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void zero_counter_kernel(unsigned long long *c, int n)
+{
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+}
+
+hipError_t launch_prep(const SweepJob &job, int j, const DevTables &T, hipStream_t s)
+{
+    long long n = job.cm[j];
+    for (int i = 0; i < 4; i++)
+        if (i != j) n *= job.m[i];
+    const unsigned grid = (unsigned)std::min<long long>((n + 255) / 256, 65536);
+    if (n == 0) return hipSuccess;
+    switch (j) {
+    case 0: hipLaunchKernelGGL(prep_kernel<0>, dim3(grid), dim3(256), 0, s, job, T); break;
+    case 1: hipLaunchKernelGGL(prep_kernel<1>, dim3(grid), dim3(256), 0, s, job, T); break;
+    case 2: hipLaunchKernelGGL(prep_kernel<2>, dim3(grid), dim3(256), 0, s, job, T); break;
+    default: hipLaunchKernelGGL(prep_kernel<3>, dim3(grid), dim3(256), 0, s, job, T); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(const SweepJob &job, const DevTables &T, hipStream_t s)
+{
+    if (job.ntiles == 0) return hipSuccess;
+    const dim3 grid((unsigned)job.ntiles), block(256);
+    switch (job.d) {
+    case 0: hipLaunchKernelGGL(sweep_kernel<0>, grid, block, job.lds_bytes, s, job, T); break;
+    case 1: hipLaunchKernelGGL(sweep_kernel<1>, grid, block, job.lds_bytes, s, job, T); break;
+    case 2: hipLaunchKernelGGL(sweep_kernel<2>, grid, block, job.lds_bytes, s, job, T); break;
+    default: hipLaunchKernelGGL(sweep_kernel<3>, grid, block, job.lds_bytes, s, job, T); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_batch(const SweepJob *dev_jobs, const long long *dev_tile_start, int njobs,
+                              long long total_tiles, int lds_bytes, unsigned long long *dev_counter,
+                              int grid, const DevTables &T, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, dev_counter, 1);
+    hipLaunchKernelGGL(sweep_batch_kernel, dim3(grid), dim3(256), lds_bytes, s, dev_jobs,
+                       dev_tile_start, njobs, total_tiles, dev_counter, T);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Endgame DAG (Section VIII: the serial solver for boards beyond the
+// database, rotations folded in by rmax only, no canonicalisation).
+//
+// For a root with e empty cells, node (t, cmask, omask) is the root with t
+// more stones: the side to move at the root on the cells of cmask, the other
+// side on omask.  Layers are solved from t = e (full board) down to t = 0.
+// Each node keeps, for its parents, A = F_parent(node) | rmax(not N) and
+// B = F_parent(node) | rmax(not W) (64 B) in a layer buffer.
+// ---------------------------------------------------------------------------
+
+int dag_lds_bytes(int e)
+{
+    return 2 * dag_layout(e).max_layer * 64;
+}
+
+struct RootInfo {
+    unsigned bm[4], wm[4];
+    int code[4];
+    int e;
+    int mover;
+    bool valid;
+};
+
+__device__ __forceinline__ RootInfo decode_root(uint64_t packed)
+{
+    RootInfo r;
+    int nb = 0, nw = 0;
+    r.valid = true;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        int code = (int)((packed >> (16 * j)) & 0xffff);
+        r.code[j] = code;
+        if (code >= 19683) { r.valid = false; code = 0; }
+        unsigned bm = 0, wm = 0;
+        int x = code;
+        for (int l = 0; l < 9; l++) {
+            const int dgt = x % 3;
+            x /= 3;
+            bm |= (unsigned)(dgt == 1) << l;
+            wm |= (unsigned)(dgt == 2) << l;
+        }
+        r.bm[j] = bm;
+        r.wm[j] = wm;
+        nb += __popc(bm);
+        nw += __popc(wm);
+    }
+    r.e = 36 - nb - nw;
+    if (nb != nw && nb != nw + 1) r.valid = false;
+    if (r.e > 10) r.valid = false;
+    r.mover = nb == nw ? 1 : 2;
+    return r;
+}
+
+// Solve one root with a group of threads (the whole workgroup).  `buf0` and
+// `buf1` hold two layers of A/B records (64 B per node).
+__device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, uint4 *buf1,
+                           uint4 *out)
+{
+    __shared__ int s_slot_q[10], s_slot_l[10];
+    if (threadIdx.x == 0) {
+        int n = 0;
+        for (int j = 0; j < 4; j++) {
+            const unsigned empt = ~(R.bm[j] | R.wm[j]) & 0x1ffu;
+            for (int l = 0; l < 9; l++)
+                if ((empt >> l) & 1) {
+                    s_slot_q[n] = j;
+                    s_slot_l[n] = l;
+                    n++;
+                }
+        }
+    }
+    __syncthreads();
+    const int e = R.e;
+    const uint32_t *nodes = T.dag_node + T.dag_node_off[e];
+    const uint16_t *rank = T.dag_rank + T.dag_rank_off[e];
+    const int *layer = T.dag_layer[e];
+    uint4 *cur = buf0, *prev = buf1;
+    for (int t = e; t >= 0; t--) {
+        const int n0 = layer[t], n1 = layer[t + 1];
+        const int x = (t & 1) ? 3 - R.mover : R.mover;   // side to move at layer t
+        const int xdigit = (t & 1) ? 2 : 1;              // slot digit of x's stones
+        for (int i = n0 + (int)threadIdx.x; i < n1; i += blockDim.x) {
+            const uint32_t nd = nodes[i];
+            const unsigned cmask = nd & 0xffffu, omask = nd >> 16;
+            unsigned bm[4] = {R.bm[0], R.bm[1], R.bm[2], R.bm[3]};
+            unsigned wm[4] = {R.wm[0], R.wm[1], R.wm[2], R.wm[3]};
+            int code = 0;
+            for (int s = e - 1; s >= 0; s--) {
+                const int q = s_slot_q[s], l = s_slot_l[s];
+                const bool isc = (cmask >> s) & 1, iso = (omask >> s) & 1;
+                // root mover's stones are black iff the root mover is black
+                const bool black = (isc && R.mover == 1) || (iso && R.mover == 2);
+                const bool white = (isc && R.mover == 2) || (iso && R.mover == 1);
+                bm[q] |= (unsigned)black << l;
+                wm[q] |= (unsigned)white << l;
+                code = 3 * code + (isc ? 1 : iso ? 2 : 0);
+            }
+            unsigned xm[4], ym[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                xm[j] = x == 1 ? bm[j] : wm[j];
+                ym[j] = x == 1 ? wm[j] : bm[j];
+            }
+            const Set256 Fx = board_five(T, xm);
+            const Set256 Fy = board_five(T, ym);
+            Set256 Wnt = s_zero(), Nnt = s_zero();
+            if (t == e) {
+                Nnt = s_full();
+            } else {
+                const unsigned free = ~(cmask | omask) & ((1u << e) - 1u);
+                unsigned f = free;
+                while (f) {
+                    const int s = __builtin_ctz(f);
+                    f &= f - 1;
+                    const int ci = rank[code + xdigit * (int)c_pow3[s]];
+                    const uint4 *p = prev + 4 * ci;
+                    Set256 A, B;
+                    const uint4 a0 = p[0], a1 = p[1], b0 = p[2], b1 = p[3];
+                    A.w[0] = a0.x; A.w[1] = a0.y; A.w[2] = a0.z; A.w[3] = a0.w;
+                    A.w[4] = a1.x; A.w[5] = a1.y; A.w[6] = a1.z; A.w[7] = a1.w;
+                    B.w[0] = b0.x; B.w[1] = b0.y; B.w[2] = b0.z; B.w[3] = b0.w;
+                    B.w[4] = b1.x; B.w[5] = b1.y; B.w[6] = b1.z; B.w[7] = b1.w;
+                    s_or_into(Wnt, A);
+                    s_or_into(Nnt, B);
+                }
+            }
+            Set256 W, N;
+            combine(Fx, Fy, Wnt, Nnt, W, N);
+            if (t == 0) {
+                store_info(out, W, N);
+            } else {
+                Set256 A, B;
+                child_terms(Fy, W, N, A, B);
+                uint4 *p = cur + 4 * (i - n0);
+                p[0] = make_uint4(A.w[0], A.w[1], A.w[2], A.w[3]);
+                p[1] = make_uint4(A.w[4], A.w[5], A.w[6], A.w[7]);
+                p[2] = make_uint4(B.w[0], B.w[1], B.w[2], B.w[3]);
+                p[3] = make_uint4(B.w[4], B.w[5], B.w[6], B.w[7]);
+            }
+        }
+        __syncthreads();
+        uint4 *tmp = cur;
+        cur = prev;
+        prev = tmp;
+    }
+}
+
+// Count roots per number of empty cells (index 11: invalid boards).
+__global__ void eval_count_kernel(const uint64_t *boards, size_t n, int *count, uint8_t *empties,
+                                  int *status, uint4 *out)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const RootInfo R = decode_root(boards[i]);
+    const int e = R.valid ? R.e : 11;
+    empties[i] = (uint8_t)e;
+    atomicAdd(&count[e], 1);
+    if (!R.valid) {
+        const uint4 z = make_uint4(0, 0, 0, 0);
+        out[4 * i] = z; out[4 * i + 1] = z; out[4 * i + 2] = z; out[4 * i + 3] = z;
+        if (status) atomicAdd(status, 1);
+    }
+}
+
+// Bucket starts, most empty cells first.
+__global__ void eval_scan_kernel(const int *count, int *start, int *cursor)
+{
+    if (threadIdx.x != 0) return;
+    int acc = 0;
+    for (int e = 10; e >= 0; e--) {
+        start[e] = acc;
+        cursor[e] = 0;
+        acc += count[e];
+    }
+    start[11] = acc;
+    cursor[11] = 0;
+}
+
+__global__ void eval_scatter_kernel(const uint8_t *empties, size_t n, const int *start, int *cursor,
+                                    int *order)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int e = empties[i];
+    if (e > 10) return;
+    const int pos = atomicAdd(&cursor[e], 1);
+    order[start[e] + pos] = (int)i;
+}
+
+__global__ void zero_ints_kernel(int *p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// Persistent solve over all valid roots, most empty cells first: workgroups
+// take roots from a device counter.  Roots with 9 or 10 empty cells keep
+// their two layers in the workgroup's slot of a global buffer (they exceed
+// LDS), the rest in LDS.
+__global__ void __launch_bounds__(256)
+    eval_persistent_kernel(const uint64_t *boards, const int *order, const int *start,
+                           unsigned long long *counter, uint4 *out, uint4 *gl, DevTables T)
+{
+    extern __shared__ uint4 lds[];
+    __shared__ long long s_item;
+    const int nvalid = start[11];
+    const int big = start[8];  // roots with 9..10 empty cells occupy [0, big)
+    uint4 *mine = gl + (size_t)blockIdx.x * 2 * 4 * kDagGlobalLayer;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (long long)atomicAdd(counter, 1ull);
+        __syncthreads();
+        const long long item = s_item;
+        __syncthreads();
+        if (item >= nvalid) break;
+        const int root = order[item];
+        const RootInfo R = decode_root(boards[root]);
+        if (item < big) {
+            solve_root(R, T, mine, mine + 4 * kDagGlobalLayer, out + 4 * (size_t)root);
+        } else {
+            solve_root(R, T, lds, lds + 4 * T.dag_max[R.e], out + 4 * (size_t)root);
+        }
+        __syncthreads();
+    }
+}
+
+// Plain form: the roots of one empties group, one workgroup per root
+// (grid-stride when the group needs global layer buffers).
+__global__ void __launch_bounds__(256)
+    eval_group_kernel(const uint64_t *boards, const int *order, int first, int count, uint4 *out,
+                      uint4 *gl, int use_global, DevTables T)
+{
+    extern __shared__ uint4 lds[];
+    uint4 *mine = gl + (size_t)blockIdx.x * 2 * 4 * kDagGlobalLayer;
+    for (int item = blockIdx.x; item < count; item += gridDim.x) {
+        const int root = order[first + item];
+        const RootInfo R = decode_root(boards[root]);
+        if (use_global)
+            solve_root(R, T, mine, mine + 4 * kDagGlobalLayer, out + 4 * (size_t)root);
+        else
+            solve_root(R, T, lds, lds + 4 * T.dag_max[R.e], out + 4 * (size_t)root);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_eval_bin(const uint64_t *boards, size_t n, const EvalScratch &S, int *status,
+                           uint4 *out, const DevTables &T, hipStream_t s)
+{
+    (void)T;
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, S.count, 16);
+    if (n) {
+        const unsigned g = (unsigned)((n + 255) / 256);
+        hipLaunchKernelGGL(eval_count_kernel, dim3(g), dim3(256), 0, s, boards, n, S.count,
+                           S.empties, status, out);
+    }
+    hipLaunchKernelGGL(eval_scan_kernel, dim3(1), dim3(64), 0, s, S.count, S.start, S.cursor);
+    if (n) {
+        const unsigned g = (unsigned)((n + 255) / 256);
+        hipLaunchKernelGGL(eval_scatter_kernel, dim3(g), dim3(256), 0, s, S.empties, n, S.start,
+                           S.cursor, S.order);
+    }
+    return hipGetLastError();
+}
+
+// Dynamic LDS above 64 KiB has to be granted per kernel.
+static hipError_t allow_lds(const void *kernel, int bytes)
+{
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t launch_eval_persistent(const uint64_t *boards, size_t n, uint4 *out,
+                                  const EvalScratch &S, int grid, const DevTables &T,
+                                  hipStream_t s)
+{
+    (void)n;
+    hipError_t e = allow_lds((const void *)eval_persistent_kernel, dag_lds_bytes(8));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, S.counter, 1);
+    hipLaunchKernelGGL(eval_persistent_kernel, dim3(grid), dim3(256), dag_lds_bytes(8), s, boards,
+                       S.order, S.start, S.counter, out, S.global_layers, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_group(const uint64_t *boards, int e, int first, int count, uint4 *out,
+                             const EvalScratch &S, const DevTables &T, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    const bool global = e > 8;
+    const int grid = global ? std::min(count, S.global_slots) : count;
+    const hipError_t err = allow_lds((const void *)eval_group_kernel, global ? 0 : dag_lds_bytes(e));
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(eval_group_kernel, dim3(grid), dim3(256), global ? 0 : dag_lds_bytes(e), s,
+                       boards, S.order, first, count, out, S.global_layers, global ? 1 : 0, T);
+    return hipGetLastError();
+}
+
+}  // namespace pg

@@ -1,0 +1,261 @@
+// set256.h -- 256-bit sets over L = Z4^4 and the rotation-abstracted
+// primitives of Section III: rmax, the five-in-a-row set over L, and the
+// cyclic shift f_b -> f_{gb} for g in L.
+//
+// A set lives in eight 32-bit words held by one lane: element
+// g = g0 + 4*g1 + 16*g2 + 64*g3 is word g >> 5 = (g2 >> 1) + 2*g3, bit
+// g & 31 = g0 + 4*g1 + 16*(g2 & 1).  So dimensions 0 and 1 are bit
+// positions inside 16-bit halves, dimension 2 picks the half and the word of
+// a pair, dimension 3 picks the word pair.  All functions are usable on the
+// host too (the library's CPU self-checks call them there).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PG_HD __host__ __device__ __forceinline__
+
+namespace pg {
+
+struct Set256 {
+    uint32_t w[8];
+};
+
+PG_HD Set256 s_zero()
+{
+    Set256 r;
+#pragma unroll
+    for (int i = 0; i < 8; i++) r.w[i] = 0;
+    return r;
+}
+
+PG_HD Set256 s_full()
+{
+    Set256 r;
+#pragma unroll
+    for (int i = 0; i < 8; i++) r.w[i] = 0xffffffffu;
+    return r;
+}
+
+PG_HD void s_or_into(Set256 &a, const Set256 &b)
+{
+#pragma unroll
+    for (int i = 0; i < 8; i++) a.w[i] |= b.w[i];
+}
+
+PG_HD Set256 s_not(const Set256 &a)
+{
+    Set256 r;
+#pragma unroll
+    for (int i = 0; i < 8; i++) r.w[i] = ~a.w[i];
+    return r;
+}
+
+PG_HD uint32_t rotr32(uint32_t x, int s) { return (x >> s) | (x << (32 - s)); }
+
+// rmax(X)(g) = OR over the 8 single-quadrant turns r of X(g + r) (Section III).
+// Along each dimension the two neighbours g_j +- 1 of g_j are the two values
+// of the other parity, so each dimension costs a pair-swap plus an OR.
+PG_HD Set256 rmax(const Set256 &x)
+{
+    Set256 r;
+    uint32_t n2[4];
+#pragma unroll
+    for (int g3 = 0; g3 < 4; g3++) n2[g3] = rotr32(x.w[2 * g3] | x.w[2 * g3 + 1], 16);
+#pragma unroll
+    for (int w = 0; w < 8; w++) {
+        const int g3 = w >> 1, p = w & 1;
+        const uint32_t u = x.w[w];
+        // dimension 0: bits inside nibbles
+        uint32_t y0 = u | (((u >> 2) & 0x33333333u) | ((u << 2) & 0xccccccccu));
+        uint32_t n0 = ((y0 >> 1) & 0x55555555u) | ((y0 << 1) & 0xaaaaaaaau);
+        // dimension 1: nibbles inside halves
+        uint32_t y1 = u | (((u >> 8) & 0x00ff00ffu) | ((u << 8) & 0xff00ff00u));
+        uint32_t n1 = ((y1 >> 4) & 0x0f0f0f0fu) | ((y1 << 4) & 0xf0f0f0f0u);
+        // dimension 3: word pairs
+        uint32_t n3 = x.w[2 * ((g3 + 1) & 3) + p] | x.w[2 * ((g3 + 3) & 3) + p];
+        r.w[w] = n0 | n1 | n2[g3] | n3;
+    }
+    return r;
+}
+
+// out(g) = in(g - k e_d): the table of a board whose quadrant d was turned k
+// more times (Section III, transform f_b -> f_{gb} with g = k e_d).
+PG_HD Set256 shift_dim(const Set256 &x, int d, int k)
+{
+    k &= 3;
+    if (k == 0) return x;
+    Set256 r;
+    if (d == 0) {
+        const uint32_t hi = 0x11111111u * ((0xfu << k) & 0xfu);
+        const uint32_t lo = 0x11111111u * (0xfu >> (4 - k));
+#pragma unroll
+        for (int w = 0; w < 8; w++) r.w[w] = ((x.w[w] << k) & hi) | ((x.w[w] >> (4 - k)) & lo);
+    } else if (d == 1) {
+        const int s = 4 * k;
+        const uint32_t hi = 0x00010001u * ((0xffffu << s) & 0xffffu);
+        const uint32_t lo = 0x00010001u * (0xffffu >> (16 - s));
+#pragma unroll
+        for (int w = 0; w < 8; w++) r.w[w] = ((x.w[w] << s) & hi) | ((x.w[w] >> (16 - s)) & lo);
+    } else if (d == 2) {
+        // halves g2 = 0..3 of each word pair rotate by k: by two halves
+        // (swap the words) then by one half (funnel shift by 16)
+#pragma unroll
+        for (int g3 = 0; g3 < 4; g3++) {
+            uint32_t a = x.w[2 * g3], b = x.w[2 * g3 + 1];
+            if (k & 2) { uint32_t t = a; a = b; b = t; }
+            if (k & 1) {
+                uint32_t na = (b >> 16) | (a << 16);
+                uint32_t nb = (a >> 16) | (b << 16);
+                a = na;
+                b = nb;
+            }
+            r.w[2 * g3] = a;
+            r.w[2 * g3 + 1] = b;
+        }
+    } else {
+        // word pairs g3 rotate by k: by one pair then by two pairs
+        uint32_t t[8];
+#pragma unroll
+        for (int w = 0; w < 8; w++) t[w] = (k & 1) ? x.w[(w + 6) & 7] : x.w[w];
+#pragma unroll
+        for (int w = 0; w < 8; w++) r.w[w] = (k & 2) ? t[(w + 4) & 7] : t[w];
+    }
+    return r;
+}
+
+// ------------------------------------------------------------------------
+// Five in a row over L (Section III: the set of g for which g.b has five in
+// a row of one colour).
+//
+// Each of the 32 lines of the board touches two or three quadrants.  For a
+// quadrant j and a line through it, mu = the 4-bit set of turns k of quadrant
+// j after which the line's cells in quadrant j all hold the colour.  The line
+// is complete at g iff g_j is in mu_j for every quadrant j it touches, so the
+// five-set is a union of products of such 4-bit sets.  Lines are grouped by
+// the quadrants they touch:
+//   rows of the top half (Q0,Q1), rows of the bottom half (Q2,Q3),
+//   columns of the left half (Q0,Q2), of the right half (Q1,Q3),
+//   the two long diagonals (Q0,Q3), the two long anti-diagonals (Q1,Q2),
+//   and four single lines touching three quadrants:
+//   T013 (Q0,Q1,Q3), T023 (Q0,Q2,Q3), T012 (Q0,Q1,Q2), T123 (Q1,Q2,Q3).
+//
+// LineMasks of one quadrant and one colour pattern (a 9-bit stone mask):
+//   a = its six lines of the first two-quadrant group, nibble i = line i
+//   b = its six lines of the second group
+//   c = nibbles 0,1: its two lines of the diagonal pair;
+//       nibble 2: T013, 3: T023, 4: T012, 5: T123 (zero where the line misses it)
+// First/second group per quadrant: Q0 (top rows, left columns),
+// Q1 (top rows, right columns), Q2 (bottom rows, left columns),
+// Q3 (bottom rows, right columns).  Diagonal pair: Q0,Q3 long diagonals;
+// Q1,Q2 long anti-diagonals.
+// ------------------------------------------------------------------------
+struct LineMasks {
+    uint32_t a, b, c;
+};
+
+PG_HD uint32_t nib(uint32_t x, int i) { return (x >> (4 * i)) & 0xfu; }
+
+// bit y of m moves to bit 4y
+PG_HD uint32_t spread1(uint32_t m)
+{
+    return (m & 1u) | ((m & 2u) << 3) | ((m & 4u) << 6) | ((m & 8u) << 9);
+}
+
+// {x + 4y : x in a, y in b}
+PG_HD uint32_t prod16(uint32_t a, uint32_t b) { return a * spread1(b); }
+
+// a set of g0 values, repeated for every g1 (16-bit half)
+PG_HD uint32_t rep_g0(uint32_t m) { return m * 0x1111u; }
+// a set of g1 values, every g0 (16-bit half)
+PG_HD uint32_t fill_g1(uint32_t m) { return spread1(m) * 0xfu; }
+
+PG_HD uint32_t union_pairs6(uint32_t lo, uint32_t hi)
+{
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < 6; i++) s |= prod16(nib(lo, i), nib(hi, i));
+    return s;
+}
+
+PG_HD uint32_t union_pairs2(uint32_t lo, uint32_t hi)
+{
+    return prod16(nib(lo, 0), nib(hi, 0)) | prod16(nib(lo, 1), nib(hi, 1));
+}
+
+// The five-set of one colour from the line masks of its four quadrants.
+PG_HD Set256 five_set(const LineMasks &q0, const LineMasks &q1, const LineMasks &q2,
+                      const LineMasks &q3)
+{
+    // two-quadrant groups, each as a 16-bit set over its two dimensions
+    const uint32_t S01 = union_pairs6(q0.a, q1.a);  // g0 + 4 g1
+    const uint32_t S23 = union_pairs6(q2.a, q3.a);  // g2 + 4 g3
+    const uint32_t S02 = union_pairs6(q0.b, q2.b);  // g0 + 4 g2
+    const uint32_t S13 = union_pairs6(q1.b, q3.b);  // g1 + 4 g3
+    const uint32_t S03 = union_pairs2(q0.c, q3.c);  // g0 + 4 g3
+    const uint32_t S12 = union_pairs2(q1.c, q2.c);  // g1 + 4 g2
+    // three-quadrant lines
+    const uint32_t P013 = prod16(nib(q0.c, 2), nib(q1.c, 2)), a3 = nib(q3.c, 2);
+    const uint32_t b0 = rep_g0(nib(q0.c, 3)), b2 = nib(q2.c, 3), b3 = nib(q3.c, 3);
+    const uint32_t P012 = prod16(nib(q0.c, 4), nib(q1.c, 4)), a2 = nib(q2.c, 4);
+    const uint32_t c1 = fill_g1(nib(q1.c, 5)), c2 = nib(q2.c, 5), c3 = nib(q3.c, 5);
+
+    uint32_t Y[4], Z[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        Y[t] = rep_g0(nib(S02, t)) | fill_g1(nib(S12, t)) | (((a2 >> t) & 1u) ? P012 : 0u) | S01;
+        Z[t] = rep_g0(nib(S03, t)) | fill_g1(nib(S13, t)) | (((a3 >> t) & 1u) ? P013 : 0u);
+    }
+    Set256 r;
+#pragma unroll
+    for (int g3 = 0; g3 < 4; g3++) {
+#pragma unroll
+        for (int p = 0; p < 2; p++) {
+            uint32_t half[2];
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int g2 = 2 * p + h;
+                uint32_t v = Y[g2] | Z[g3];
+                v |= ((S23 >> (g2 + 4 * g3)) & 1u) ? 0xffffu : 0u;
+                v |= (((b2 >> g2) & (b3 >> g3)) & 1u) ? b0 : 0u;
+                v |= (((c2 >> g2) & (c3 >> g3)) & 1u) ? c1 : 0u;
+                half[h] = v;
+            }
+            r.w[2 * g3 + p] = half[0] | (half[1] << 16);
+        }
+    }
+    return r;
+}
+
+// ------------------------------------------------------------------------
+// Value assembly (Section II recurrence on Section III tables).
+//   Fc, Fo     five-sets of the side to move and of the other side
+//   Wnt, Nnt   OR over children of (immediate win | rmax(not child N)) and
+//              (immediate win | rmax(not child W))
+// Terminal elements (a five of either colour) score f_c - f_cbar; the rest
+// take the children.  W = notFo & (Fc | Wnt), N = Fc | (notFo & Nnt).
+// ------------------------------------------------------------------------
+PG_HD void combine(const Set256 &Fc, const Set256 &Fo, const Set256 &Wnt, const Set256 &Nnt,
+                   Set256 &W, Set256 &N)
+{
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        W.w[i] = ~Fo.w[i] & (Fc.w[i] | Wnt.w[i]);
+        N.w[i] = Fc.w[i] | (~Fo.w[i] & Nnt.w[i]);
+    }
+}
+
+// The two sets a parent ORs in for one child t (side to move in t = the
+// parent's opponent): A = F_parent(t) | rmax(not N_t), B = F_parent(t) | rmax(not W_t).
+PG_HD void child_terms(const Set256 &Fparent_t, const Set256 &Wt, const Set256 &Nt, Set256 &A,
+                       Set256 &B)
+{
+    Set256 a = rmax(s_not(Nt));
+    Set256 b = rmax(s_not(Wt));
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        A.w[i] = Fparent_t.w[i] | a.w[i];
+        B.w[i] = Fparent_t.w[i] | b.w[i];
+    }
+}
+
+}  // namespace pg

@@ -1,0 +1,220 @@
+// tables.cpp -- construction of the host-side quadrant and DAG tables.
+#include "tables.h"
+
+#include <algorithm>
+#include <mutex>
+
+namespace pg {
+
+int popcount9(unsigned x)
+{
+    int n = 0;
+    for (; x; x &= x - 1) n++;
+    return n;
+}
+
+static int pow3(int l)
+{
+    int p = 1;
+    while (l-- > 0) p *= 3;
+    return p;
+}
+
+// local cell after one counter-clockwise turn: (lr, lc) -> (2 - lc, lr)
+static int turn_cell(int l)
+{
+    const int lr = l / 3, lc = l % 3;
+    return 3 * (2 - lc) + lr;
+}
+
+static unsigned turn_mask(unsigned m, int k)
+{
+    for (int t = 0; t < k; t++) {
+        unsigned r = 0;
+        for (int l = 0; l < 9; l++)
+            if (m >> l & 1) r |= 1u << turn_cell(l);
+        m = r;
+    }
+    return m;
+}
+
+// The 32 lines of the board with the field/nibble each quadrant keeps them in
+// (layout documented at LineMasks in set256.h).
+struct LineDef {
+    int cells[5];
+    int group;  // 0 rows top, 1 rows bottom, 2 cols left, 3 cols right, 4 diag, 5 anti, 6.. triples
+    int slot;   // index inside a two-quadrant group; triple id for groups >= 6
+};
+
+static std::vector<LineDef> all_lines()
+{
+    std::vector<LineDef> out;
+    for (int r = 0; r < 6; r++)
+        for (int c0 = 0; c0 < 2; c0++) {
+            LineDef d;
+            for (int i = 0; i < 5; i++) d.cells[i] = 6 * r + c0 + i;
+            d.group = r < 3 ? 0 : 1;
+            d.slot = 2 * (r % 3) + c0;
+            out.push_back(d);
+        }
+    for (int c = 0; c < 6; c++)
+        for (int r0 = 0; r0 < 2; r0++) {
+            LineDef d;
+            for (int i = 0; i < 5; i++) d.cells[i] = 6 * (r0 + i) + c;
+            d.group = c < 3 ? 2 : 3;
+            d.slot = 2 * (c % 3) + r0;
+            out.push_back(d);
+        }
+    // diagonals down-right from (r0, c0)
+    const int diag[4][2] = {{0, 0}, {1, 1}, {0, 1}, {1, 0}};
+    for (int k = 0; k < 4; k++) {
+        LineDef d;
+        for (int i = 0; i < 5; i++) d.cells[i] = 6 * (diag[k][0] + i) + diag[k][1] + i;
+        if (k < 2) { d.group = 4; d.slot = k; }
+        else { d.group = 6; d.slot = k == 2 ? 0 : 1; }  // (0,1): T013, (1,0): T023
+        out.push_back(d);
+    }
+    // anti-diagonals down-left from (r0, c0)
+    const int anti[4][2] = {{0, 5}, {1, 4}, {0, 4}, {1, 5}};
+    for (int k = 0; k < 4; k++) {
+        LineDef d;
+        for (int i = 0; i < 5; i++) d.cells[i] = 6 * (anti[k][0] + i) + anti[k][1] - i;
+        if (k < 2) { d.group = 5; d.slot = k; }
+        else { d.group = 6; d.slot = k == 2 ? 2 : 3; }  // (0,4): T012, (1,5): T123
+        out.push_back(d);
+    }
+    return out;
+}
+
+static void build_line_masks(HostTables &t)
+{
+    t.lm.assign(4 * 512, LineMasks{0, 0, 0});
+    const std::vector<LineDef> lines = all_lines();
+    for (const LineDef &d : lines) {
+        for (int q = 0; q < 4; q++) {
+            unsigned cells = 0;
+            for (int i = 0; i < 5; i++) {
+                const int r = d.cells[i] / 6, c = d.cells[i] % 6;
+                if (2 * (r / 3) + c / 3 == q) cells |= 1u << (3 * (r % 3) + c % 3);
+            }
+            if (!cells) continue;
+            // which field/nibble of quadrant q's record holds this line
+            int field, pos;
+            if (d.group < 4) {
+                const bool first = (d.group == 0 || d.group == 1);  // rows are field a
+                field = first ? 0 : 1;
+                pos = d.slot;
+            } else if (d.group < 6) {
+                field = 2;
+                pos = d.slot;
+            } else {
+                field = 2;
+                pos = 2 + d.slot;
+            }
+            for (unsigned m = 0; m < 512; m++) {
+                unsigned mu = 0;
+                for (int k = 0; k < 4; k++)
+                    if ((turn_mask(m, k) & cells) == cells) mu |= 1u << k;
+                LineMasks &rec = t.lm[q * 512 + m];
+                uint32_t &f = field == 0 ? rec.a : field == 1 ? rec.b : rec.c;
+                f |= mu << (4 * pos);
+            }
+        }
+    }
+}
+
+static void build(HostTables &t)
+{
+    const int NC = 19683;
+    t.turn1.resize(NC);
+    for (int code = 0; code < NC; code++) {
+        int r = 0;
+        for (int l = 0; l < 9; l++) r += (code / pow3(l)) % 3 * pow3(turn_cell(l));
+        t.turn1[code] = (uint16_t)r;
+    }
+    std::vector<int> minc(NC), mink(NC);
+    for (int code = 0; code < NC; code++) {
+        int best = code, bk = 0, cur = code;
+        for (int k = 1; k < 4; k++) {
+            cur = t.turn1[cur];
+            if (cur < best) { best = cur; bk = k; }
+        }
+        minc[code] = best;
+        mink[code] = bk;
+    }
+    std::vector<int> index(NC, -1);
+    t.qinfo.clear();
+    for (int b = 0; b <= 9; b++)
+        for (int w = 0; w <= 9; w++) {
+            t.class_start[b][w] = (int)t.qinfo.size();
+            t.class_size[b][w] = 0;
+            if (b + w > 9) continue;
+            for (int code = 0; code < NC; code++) {
+                if (minc[code] != code) continue;
+                unsigned bm = 0, wm = 0;
+                for (int l = 0; l < 9; l++) {
+                    const int dgt = (code / pow3(l)) % 3;
+                    if (dgt == 1) bm |= 1u << l;
+                    if (dgt == 2) wm |= 1u << l;
+                }
+                if (popcount9(bm) != b || popcount9(wm) != w) continue;
+                index[code] = t.class_size[b][w]++;
+                t.qinfo.push_back(QInfo{(uint16_t)code, (uint16_t)bm, (uint16_t)wm, 0});
+            }
+        }
+    t.canon.resize(NC);
+    for (int code = 0; code < NC; code++)
+        t.canon[code] = (uint16_t)(index[minc[code]] | (mink[code] << 12));
+    build_line_masks(t);
+}
+
+const HostTables &host_tables()
+{
+    static HostTables t;
+    static std::once_flag once;
+    std::call_once(once, [] { build(t); });
+    return t;
+}
+
+static void build_dag(DagLayout &L, int e)
+{
+    L.e = e;
+    int n3 = 1;
+    for (int i = 0; i < e; i++) n3 *= 3;
+    L.rank.assign(n3, 0xffff);
+    L.layer_start.assign(e + 2, 0);
+    L.node.clear();
+    L.max_layer = 0;
+    for (int t = 0; t <= e; t++) {
+        L.layer_start[t] = (int)L.node.size();
+        const int nc = (t + 1) / 2, no = t / 2;
+        for (unsigned filled = 0; filled < (1u << e); filled++) {
+            if (popcount9(filled) != t) continue;
+            for (unsigned cm = filled;; cm = (cm - 1) & filled) {
+                if (popcount9(cm) == nc) {
+                    const unsigned om = filled & ~cm;
+                    (void)no;
+                    int code = 0;
+                    for (int s = e - 1; s >= 0; s--) code = 3 * code + ((cm >> s & 1) ? 1 : (om >> s & 1) ? 2 : 0);
+                    L.rank[code] = (uint16_t)(L.node.size() - L.layer_start[t]);
+                    L.node.push_back(cm | (om << 16));
+                }
+                if (cm == 0) break;
+            }
+        }
+        L.max_layer = std::max(L.max_layer, (int)L.node.size() - L.layer_start[t]);
+    }
+    L.layer_start[e + 1] = (int)L.node.size();
+}
+
+const DagLayout &dag_layout(int e)
+{
+    static DagLayout L[11];
+    static std::once_flag once;
+    std::call_once(once, [] {
+        for (int k = 0; k <= 10; k++) build_dag(L[k], k);
+    });
+    return L[e];
+}
+
+}  // namespace pg

@@ -1,0 +1,53 @@
+// tables.h -- quadrant tables of the library (Section IV: rotation-minimal
+// quadrant patterns per (black, white) class and their ordering; Section III:
+// per-quadrant line masks for the five-in-a-row sets over L).
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+#include "set256.h"
+
+namespace pg {
+
+// One rotation-minimal quadrant pattern.
+struct QInfo {
+    uint16_t code;   // ternary code, digit 0 empty / 1 black / 2 white at 3^local
+    uint16_t bm, wm; // 9-bit black and white stone masks
+    uint16_t pad;
+};
+
+struct HostTables {
+    int class_start[10][10];
+    int class_size[10][10];
+    std::vector<QInfo> qinfo;     // 4995 patterns, class by class, increasing code
+    std::vector<uint16_t> canon;  // per code: index in its class | (k << 12), where
+                                  // k = least number of turns taking the code to
+                                  // its class representative
+    std::vector<uint16_t> turn1;  // per code: code after one counter-clockwise turn
+    std::vector<LineMasks> lm;    // [quadrant * 512 + stone mask]
+};
+
+// Built once on first use (thread-safe).
+const HostTables &host_tables();
+
+// Endgame DAG layout for a board with e empty cells (the serial solver of
+// Section VIII): node (t, cmask, omask) has t stones placed in the empty
+// cells, alternately by the side to move (cmask, ceil(t/2) cells) and the
+// other side (omask, floor(t/2) cells).  Layer t holds C(e,t)*C(t,floor(t/2))
+// nodes.  Nodes are stored layer by layer; rank[] maps a ternary slot
+// assignment (digit 1 = mover, 2 = other, base 3 over slots) to the node's
+// index within its layer.
+struct DagLayout {
+    int e;
+    std::vector<int> layer_start;   // e + 2 entries
+    std::vector<uint32_t> node;     // cmask | omask << 16, layer by layer
+    std::vector<uint16_t> rank;     // 3^e entries
+    int max_layer;
+};
+
+const DagLayout &dag_layout(int e);
+
+int popcount9(unsigned x);
+
+}  // namespace pg

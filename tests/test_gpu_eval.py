@@ -1,0 +1,100 @@
+"""GPU parity of the endgame solver (pentago_eval_batch, the Section VIII
+serial solver run per board on the device) against O2 (minimax over the
+Section II rules), bit for bit.  Covers 0..10 empty cells (the LDS and the
+global layer paths), boards that already show fives, invalid boards, the
+persistent and the grouped launch forms and their equality."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1404_0743_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1404_0743_amd import pentago
+    pentago.lib()
+    return pentago
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_eval(P, boards, grouped=False):
+    codes = P.boards_to_codes(boards)
+    dev = torch.from_numpy(codes.view(np.int16).copy()).cuda()
+    out = torch.empty((len(boards), 8), dtype=torch.int64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    P.pentago_eval_batch(dev, out, status, grouped=grouped)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint64), int(status.item())
+
+
+def test_endgame_roots_33_stones(P):
+    """The 4096 seeded boards with 17 black and 16 white stones, all checked."""
+    log("33-stone roots")
+    boards = I.random_placement_boards(4096, 17, 16)
+    got, bad = gpu_eval(P, boards)
+    assert bad == 0
+    want = O.minimax_tables(boards)
+    assert np.array_equal(got, want)
+
+
+def test_mixed_empties_and_forms(P):
+    log("mixed empties")
+    boards = I.random_play_boards(3000, 28, 35, seed=21)
+    full = I.random_placement_boards(40, 18, 18, seed=22)
+    # boards that already show five in a row (17 black, 16 white, no rejection)
+    rng = np.random.default_rng(23)
+    five = []
+    while len(five) < 20:
+        b = np.zeros(36, np.uint8)
+        perm = rng.permutation(36)
+        b[perm[:17]], b[perm[17:33]] = 1, 2
+        if O.five(b, 1) or O.five(b, 2):
+            five.append(b)
+    allb = np.concatenate([boards, full, np.array(five)])
+    got, bad = gpu_eval(P, allb)
+    assert bad == 0
+    got2, _ = gpu_eval(P, allb, grouped=True)
+    assert np.array_equal(got, got2)
+    rng = np.random.default_rng(3)
+    pick = np.concatenate([rng.choice(len(boards), 300, replace=False), np.arange(len(boards), len(allb))])
+    want = O.minimax_tables(allb[pick])
+    assert np.array_equal(got[pick], want)
+
+
+def test_deep_roots_global_layers(P):
+    log("deep roots")
+    boards = np.concatenate([I.random_play_boards(3, 27, 27, seed=31),
+                             I.random_play_boards(2, 26, 26, seed=32)])
+    got, bad = gpu_eval(P, boards)
+    assert bad == 0
+    got2, _ = gpu_eval(P, boards, grouped=True)
+    assert np.array_equal(got, got2)
+    want = O.minimax_tables(boards)
+    assert np.array_equal(got, want)
+
+
+def test_invalid_boards_are_counted(P):
+    log("invalid boards")
+    good = I.random_placement_boards(5, 17, 16, seed=41)
+    bad = good.copy()
+    bad[:, :] = 0
+    bad[:, :3] = 2  # white ahead of black
+    many = np.zeros((1, 36), np.uint8)  # 36 empty cells: more than 10
+    allb = np.concatenate([good, bad, many])
+    got, nbad = gpu_eval(P, allb)
+    assert nbad == 6
+    assert not got[5:].any()
+    assert np.array_equal(got[:5], O.minimax_tables(good))

@@ -1,0 +1,196 @@
+"""GPU parity of the section sweep (pentago_solve_section) against the oracle's
+plain section retrograde O4, bit for bit (integer/bitset work: tolerance 0).
+
+Cases: sections with 36, 35, 34 and 33 stones (one, two and three quadrants
+with empty cells; the staged and the prepared child paths), ragged 8^4
+blocks, child tables from the GPU itself and random child tables (Section
+VII: random values in a slice, both algorithms compared), and the full
+1.26e9-position section (5,4),(4,5),(5,4),(4,4) on sampled entries."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1404_0743_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1404_0743_amd import pentago
+    pentago.lib()
+    return pentago
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(table):
+    return torch.from_numpy(np.ascontiguousarray(table).view(np.int64)).cuda()
+
+
+def from_dev(t):
+    return t.cpu().numpy().view(np.uint64).reshape(-1, 8)
+
+
+def gpu_solve(P, counts, children):
+    n = O.section_entries(counts)
+    out = torch.empty((n, 8), dtype=torch.int64, device="cuda")
+    P.pentago_solve_section(counts, children, out)
+    torch.cuda.synchronize()
+    return out
+
+
+def oracle_chain(counts, cache):
+    if counts in cache:
+        return cache[counts]
+    stones = sum(b + w for b, w in counts)
+    ch = [None] * 4
+    if stones < 35:
+        for j in range(4):
+            if sum(counts[j]) < 9:
+                ch[j] = oracle_chain(O.child_counts(counts, j), cache)
+    cache[counts] = O.section_solve(counts, ch)
+    return cache[counts]
+
+
+def gpu_chain(P, counts, cache):
+    """GPU tables of a section and its whole child chain (36-stone sections
+    by the terminal path, everything else by the sweep)."""
+    if counts in cache:
+        return cache[counts]
+    ch = [None] * 4
+    for j in range(4):
+        if sum(counts[j]) < 9:
+            ch[j] = gpu_chain(P, O.child_counts(counts, j), cache)
+    cache[counts] = gpu_solve(P, counts, ch)
+    return cache[counts]
+
+
+FULL36 = [((5, 4), (4, 5), (5, 4), (4, 5)), ((9, 0), (0, 9), (5, 4), (4, 5)),
+          ((1, 8), (8, 1), (6, 3), (3, 6))]
+
+
+@pytest.mark.parametrize("counts", FULL36, ids=str)
+def test_terminal_sections(P, counts):
+    log("terminal", counts)
+    got = from_dev(gpu_solve(P, counts, [None] * 4))
+    n = len(got)
+    rng = np.random.default_rng(1)
+    idx_all = O.section_all_indices(counts)
+    pick = np.sort(rng.choice(n, size=min(n, 3000), replace=False))
+    want = O.section_solve(counts, [None] * 4, idx_all[pick])
+    assert np.array_equal(got[pick], want)
+
+
+SMALL = [((7, 2), (2, 7), (1, 7), (8, 1)),        # 35 stones, empties in quadrant 2
+         ((9, 0), (0, 8), (3, 6), (6, 3)),        # 35 stones, empties in quadrant 1
+         ((8, 0), (2, 7), (2, 7), (6, 3)),        # 35 stones, empties in quadrant 0
+         ((7, 1), (2, 7), (1, 8), (7, 1)),        # 34: quadrants 0 and 3
+         ((7, 1), (1, 7), (2, 7), (7, 1)),        # 33: quadrants 0, 1, 3
+         ((8, 0), (0, 8), (1, 8), (8, 0))]        # 33: quadrants 0, 1, 3
+
+
+@pytest.mark.parametrize("counts", SMALL, ids=str)
+def test_small_sections_full_parity(P, counts):
+    log("small", counts)
+    ocache, gcache = {}, {}
+    want = oracle_chain(counts, ocache)
+    got = from_dev(gpu_chain(P, counts, gcache))
+    assert got.shape == want.shape
+    bad = np.nonzero((got != want).any(axis=1))[0]
+    assert len(bad) == 0, "first mismatching entries %s" % bad[:10]
+
+
+def periodic(counts, tables):
+    """Make random tables consistent with the symmetry of the entry's
+    quadrant patterns: a pattern invariant under t turns makes its table
+    periodic with period t along that dimension (Section III)."""
+    idx = O.section_all_indices(counts)
+    bits = O.table_bits(tables).reshape(-1, 2, 4, 4, 4, 4)  # g3 g2 g1 g0
+    for e, t in zip(idx, bits):
+        for j, (b, w) in enumerate(counts):
+            code = O.class_codes(b, w)[e[j]]
+            period = 4
+            for p in (1, 2):
+                if O.code_turn(code, p) == code:
+                    period = p
+                    break
+            if period < 4:
+                ax = 4 - j  # axis of g_j in (2, g3, g2, g1, g0)
+                sl = [slice(None)] * 5
+                sl[ax] = slice(0, period)
+                base = t[tuple(sl)]
+                reps = [1] * 5
+                reps[ax] = 4 // period
+                t[...] = np.tile(base, reps)
+    packed = np.packbits(bits.reshape(len(tables), 512), axis=1, bitorder="little")
+    return np.ascontiguousarray(packed).view(np.uint64).reshape(-1, 8)
+
+
+@pytest.mark.parametrize("counts", [((7, 1), (2, 7), (1, 8), (7, 1)),
+                                    ((6, 2), (2, 7), (1, 7), (8, 0))], ids=str)
+def test_random_child_tables(P, counts):
+    """Random (win subset of not-lose) child tables: GPU and O4 read the same
+    inputs, so they must agree on every bit whatever the values."""
+    log("random children", counts)
+    children_np = [None] * 4
+    for j in range(4):
+        if sum(counts[j]) < 9:
+            cc = O.child_counts(counts, j)
+            raw = I.random_tables(O.section_entries(cc), seed=100 + j)
+            children_np[j] = periodic(cc, raw)
+    want = O.section_solve(counts, children_np)
+    got = from_dev(gpu_solve(P, counts, [None if c is None else to_dev(c) for c in children_np]))
+    assert np.array_equal(got, want)
+
+
+CONFIG2 = ((5, 4), (4, 5), (5, 4), (4, 4))
+
+
+def test_config_section_sampled(P):
+    """The full (5,4),(4,5),(5,4),(4,4) section (6,288,640 entries), child
+    section materialised on the GPU, in the launch the benchmark times;
+    sampled entries against O4 (on-demand 36-stone children), every entry
+    checked for win subset of not-lose."""
+    log("config section")
+    child_counts = O.child_counts(CONFIG2, 3)
+    child = gpu_solve(P, child_counts, [None] * 4)
+    out = gpu_solve(P, CONFIG2, [None, None, None, child])
+    got = from_dev(out)
+    assert len(got) == 6288640
+    w, n = got[:, :4], got[:, 4:]
+    assert not (w & ~n).any()
+    rng = np.random.default_rng(7)
+    shape = O.section_shape(CONFIG2)
+    idx = np.stack([rng.integers(0, m, 1500) for m in shape], axis=1).astype(np.int32)
+    idx = np.concatenate([idx, np.array([[33, 33, 33, 159], [0, 0, 0, 0], [32, 33, 32, 158]], np.int32)])
+    want = O.section_solve(CONFIG2, [None] * 4, idx)
+    offs = np.array([O.section_offset(CONFIG2, t) for t in idx])
+    assert np.array_equal(got[offs], want)
+    # the child table the sweep read, sampled too
+    cg = from_dev(child)
+    cidx = np.stack([rng.integers(0, 34, 500) for _ in range(4)], axis=1).astype(np.int32)
+    coffs = np.array([O.section_offset(child_counts, t) for t in cidx])
+    assert np.array_equal(cg[coffs], O.section_solve(child_counts, [None] * 4, cidx))
+    # on-demand children give the same bytes as the materialised ones
+    out2 = gpu_solve(P, CONFIG2, [None] * 4)
+    assert torch.equal(out, out2)
+
+
+def test_errors(P):
+    out = torch.empty((10, 8), dtype=torch.int64, device="cuda")
+    with pytest.raises(P.PentagoError) as e:
+        P.pentago_solve_section(((7, 1), (2, 7), (1, 8), (7, 1)), [None] * 4, out)
+    assert e.value.code == P.ENOCHILD
+    with pytest.raises(P.PentagoError) as e:
+        P.pentago_solve_section(((7, 1), (2, 7), (1, 8), (8, 2)), [None] * 4, out)
+    assert e.value.code == P.EINVAL

@@ -1,0 +1,121 @@
+"""CPU checks of the HIP library: it loads, exports every symbol its headers
+declare, its layout calls agree with the oracle's, and its rotation-abstracted
+primitives (run on the host from the same source as the kernels) agree with
+their per-bit definitions (Section III: rmax, five-sets over L, the shift
+f_b -> f_gb)."""
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1404_0743_amd import pentago as P
+from paper_1404_0743_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(pentago_\w+)\s*\(", src))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_function():
+    L = P.lib()
+    names = header_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+COUNTS = [((5, 4), (4, 5), (5, 4), (4, 4)), ((7, 1), (2, 7), (1, 8), (7, 1)),
+          ((1, 1), (0, 2), (2, 1), (2, 0)), ((3, 3), (3, 3), (3, 2), (2, 3))]
+
+
+@pytest.mark.parametrize("counts", COUNTS, ids=str)
+def test_layout_matches_oracle(counts):
+    shape, entries, positions = P.pentago_section_shape(counts)
+    assert shape == O.section_shape(counts)
+    assert entries == O.section_entries(counts)
+    assert positions == I.section_positions(counts)
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        idx = [int(rng.integers(0, m)) for m in shape]
+        assert P.pentago_section_offset(counts, idx) == O.section_offset(counts, idx)
+        codes = P.pentago_section_board(counts, idx)
+        assert tuple(P.boards_to_codes(O.section_board(counts, idx)[None])[0]) == codes
+
+
+def test_child_section_and_errors():
+    counts = ((5, 4), (4, 5), (5, 4), (4, 4))
+    assert P.pentago_child_section(counts, 3) == ((5, 4), (4, 5), (5, 4), (4, 5))
+    with pytest.raises(P.PentagoError):
+        P.pentago_child_section(counts, 0)
+    with pytest.raises(P.PentagoError):
+        P.pentago_section_shape(((5, 4), (4, 5), (5, 4), (5, 4)))
+
+
+def bits_of(words):
+    return np.unpackbits(np.asarray(words, dtype=np.uint64).view(np.uint8), bitorder="little").astype(bool)
+
+
+def words_of(bits):
+    return np.packbits(np.asarray(bits, dtype=np.uint8), bitorder="little").view(np.uint64)
+
+
+def g_add(g, j, k):
+    gj = ((g >> (2 * j)) + k) & 3
+    return (g & ~(3 << (2 * j))) | (gj << (2 * j))
+
+
+def test_five_set_matches_boards():
+    rng = np.random.default_rng(2)
+    boards = I.random_placement_boards(150, 15, 14, seed=3)
+    boards = np.concatenate([boards, I.random_placement_boards(100, 9, 9, seed=4)])
+    codes = P.boards_to_codes(boards)
+    hits = 0
+    for b, c in zip(boards, codes):
+        for color in (1, 2):
+            got = bits_of(P.pentago_debug_five(c, color))
+            want = np.array([O.five(O.apply(b, g), color) for g in range(256)], bool)
+            assert np.array_equal(got, want)
+            hits += want.sum()
+    assert hits > 1000
+
+
+def test_rmax_matches_definition():
+    rng = np.random.default_rng(5)
+    for density in (0.02, 0.1, 0.5):
+        for _ in range(50):
+            x = rng.random(256) < density
+            got = bits_of(P.pentago_debug_rmax(words_of(x)))
+            want = np.array([any(x[g_add(g, j, s)] for j in range(4) for s in (1, 3))
+                             for g in range(256)])
+            assert np.array_equal(got, want)
+
+
+def test_shift_matches_definition():
+    rng = np.random.default_rng(6)
+    for _ in range(40):
+        x = rng.random(256) < 0.5
+        for d in range(4):
+            for k in range(4):
+                got = bits_of(P.pentago_debug_shift(words_of(x), d, k))
+                want = np.array([x[g_add(g, d, -k)] for g in range(256)])
+                assert np.array_equal(got, want)
+
+
+def test_canon_matches_oracle():
+    for code in range(0, 19683, 7):
+        m, k = O.canon(code)
+        digits = [(m // 3 ** l) % 3 for l in range(9)]
+        b, w = digits.count(1), digits.count(2)
+        idx, kk = P.pentago_debug_canon(code)
+        assert kk == k
+        assert O.class_codes(b, w)[idx] == m
