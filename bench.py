@@ -1,0 +1,159 @@
+"""Benchmark of the n+1 -> n retrograde sweep on one MI355X.
+
+Workload (one step): the sweep of the section whose quadrants hold
+(black, white) = (5,4),(4,5),(5,4),(4,4), white to move: 6,288,640 entries,
+1,260,236,880 positions, reading its 36-stone child section
+(5,4),(4,5),(5,4),(4,5) (1,336,336 entries) which is materialised on the
+GPU before the timed region.  Inputs are resident in HBM when timing starts.
+
+Prints one JSON line: throughput in positions/s, the roofline of the sweep
+kernel (algorithmic bytes over HIP-event time on the launch stream) and the
+CPU oracle timed on a bounded sample of the same section.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extra]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "positions/sec of n+1->n retrograde sweep (bit-exact) + p50/p99 query latency"
+SECTION = ((5, 4), (4, 5), (5, 4), (4, 4))
+CHILD = ((5, 4), (4, 5), (5, 4), (4, 5))
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(entries, positions, seconds_target=15.0):
+    """The oracle (O4, per-entry plain retrograde) on a bounded random sample
+    of the section's entries, on the host cores; scaled to positions/s."""
+    import oracle as O
+    threads = min(16, os.cpu_count() or 1)
+    rng = np.random.default_rng(12345)
+    shape = O.section_shape(SECTION)
+    # calibrate on a small sample, then size the main sample to ~seconds_target
+    n = 256
+    while True:
+        idx = np.stack([rng.integers(0, m, n) for m in shape], axis=1).astype(np.int32)
+        t0 = time.perf_counter()
+        O.section_solve(SECTION, [None] * 4, idx, nthreads=threads)
+        dt = time.perf_counter() - t0
+        if dt > 2.0 or n >= 1 << 20:
+            break
+        n = int(n * min(8.0, max(2.0, seconds_target / max(dt, 1e-3))))
+    pos_per_entry = positions / entries
+    return {"value": n * pos_per_entry / dt, "unit": "positions/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d random entries of the section (%.0f positions), plain per-entry "
+                      "retrograde on concrete boards, %d threads, %.1f s" % (n, n * pos_per_entry, threads, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--extra", action="store_true", help="also time the other workloads")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 512 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the sweep would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1404_0743_amd import pentago as P
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    shape, entries, positions = P.pentago_section_shape(SECTION)
+    cshape, centries, _ = P.pentago_section_shape(CHILD)
+    child = torch.empty((centries, 8), dtype=torch.int64, device="cuda")
+    out = torch.empty((entries, 8), dtype=torch.int64, device="cuda")
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    P.pentago_solve_section(CHILD, [None] * 4, child, stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    terminal_ms = t0.elapsed_time(t1)
+    children = [None, None, None, child]
+
+    for _ in range(args.warmup):
+        P.pentago_solve_section(SECTION, children, out, stream)
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        P.pentago_solve_section(SECTION, children, out, stream)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    kernel_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    if args.copy_calibration:
+        src = torch.ones(1 << 26, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    avg_ms = float(np.mean(kernel_ms))
+    ms_per_step = 1000.0 * wall / args.steps
+
+    # algorithmic bytes of one sweep: every parent superinfo written once,
+    # every child superinfo read once
+    alg_bytes = 64 * entries + 64 * centries
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+    if os.path.exists(tfile):
+        with open(tfile) as f:
+            traffic = json.load(f).get("bytes_per_launch")
+
+    res = {
+        "metric": METRIC,
+        "value": positions / (ms_per_step * 1e-3),
+        "unit": "positions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "single-section sweep 36->35: section (5,4),(4,5),(5,4),(4,4) "
+                               "white to move, %d entries, %d positions, child section "
+                               "(5,4),(4,5),(5,4),(4,5) %d entries resident" % (entries, positions, centries),
+                   "entries": entries, "positions": positions, "shape": list(shape)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "kernel_ms": {"sweep_avg": avg_ms, "sweep_min": float(np.min(kernel_ms)),
+                      "terminal_child_section": terminal_ms},
+    }
+    if args.extra:
+        import bench_extra
+        res["extra"] = bench_extra.run_all(P, torch, stream)
+    if not args.no_cpu:
+        log("timing the CPU oracle on a sample ...")
+        res["cpu_baseline"] = cpu_baseline(entries, positions)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -28,6 +28,11 @@ int pentago_debug_rmax(const pentago_set256 *in, pentago_set256 *out);
  * more times counter-clockwise (Section III, f_b -> f_gb for g in L). */
 int pentago_debug_shift(const pentago_set256 *in, int d, int k, pentago_set256 *out);
 
+/* out(g') = in(g) where g' is g with coordinates d and 3 exchanged: the
+ * internal layout the sweep kernels work in when quadrant d receives the
+ * stones (self-inverse; identity for d = 3). */
+int pentago_debug_swap3(const pentago_set256 *in, int d, pentago_set256 *out);
+
 /* Rotation-minimal pattern of a quadrant code: its index in its (black,
  * white) class and the least number of counter-clockwise turns k taking the
  * code to it (Section IV). */

@@ -67,12 +67,15 @@ int device_tables(DevTables *out)
         size_t bytes;
         void **dst;
     };
-    void *canon, *qinfo, *lm, *dn, *dr;
+    void *canon, *qinfo, *lm, *dn, *dr, *sel, *cref, *uref;
     Up ups[] = {{H.canon.data(), H.canon.size() * 2, &canon},
                 {H.qinfo.data(), H.qinfo.size() * sizeof(QInfo), &qinfo},
                 {H.lm.data(), H.lm.size() * sizeof(LineMasks), &lm},
                 {nodes.data(), nodes.size() * 4, &dn},
-                {ranks.data(), ranks.size() * 2, &dr}};
+                {ranks.data(), ranks.size() * 2, &dr},
+                {H.sel.data(), H.sel.size() * 4, &sel},
+                {H.chunk_ref.data(), H.chunk_ref.size() * 2, &cref},
+                {H.u_ref.data(), H.u_ref.size() * 4, &uref}};
     for (Up &u : ups) {
         e = hipMalloc(&p, u.bytes);
         if (e != hipSuccess) return hip_fail(e, "hipMalloc(tables)");
@@ -85,6 +88,9 @@ int device_tables(DevTables *out)
     T.lm = (const LineMasks *)lm;
     T.dag_node = (const uint32_t *)dn;
     T.dag_rank = (const uint16_t *)dr;
+    T.sel = (const uint4 *)sel;
+    T.chunk_ref = (const uint16_t *)cref;
+    T.u_ref = (const uint32_t *)uref;
     g_dev_tables[dev] = T;
     *out = T;
     return 0;
@@ -203,11 +209,11 @@ int make_job(const pentago_section &s, const pentago_superinfo *const child[4],
     int G = 8;
     if (forceG > 0) G = forceG;
     else
-        while (G > 1 && G * cmd * 64 > 65536) G >>= 1;
+        while (G > 1 && sweep_lds_bytes(G, cmd) > 65536) G >>= 1;
     J->G = G;
     J->ngroups = (J->m[J->e] + G - 1) / G;
     J->ntiles = (long long)J->m[J->o1] * J->m[J->o2] * J->ngroups;
-    J->lds_bytes = G * cmd * 64;
+    J->lds_bytes = sweep_lds_bytes(G, cmd);
     J->out = (uint4 *)out;
     return 0;
 }

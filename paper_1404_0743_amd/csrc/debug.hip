@@ -50,6 +50,15 @@ int pentago_debug_shift(const pentago_set256 *in, int d, int k, pentago_set256 *
     return 0;
 }
 
+int pentago_debug_swap3(const pentago_set256 *in, int d, pentago_set256 *out)
+{
+    if (!in || !out || d < 0 || d > 3) return fail(PENTAGO_EINVAL, "invalid arguments");
+    Set256 x = from_abi(in);
+    swap_with3_rt(x, d);
+    to_abi(x, out);
+    return 0;
+}
+
 int pentago_debug_canon(int code, int *index, int *k)
 {
     if (code < 0 || code >= 19683 || !index || !k) return fail(PENTAGO_EINVAL, "invalid arguments");

@@ -14,6 +14,9 @@ struct DevTables {
     const uint16_t *canon;   // [19683] index in class | k << 12
     const QInfo *qinfo;      // [4995]
     const LineMasks *lm;     // [4 * 512]
+    const uint4 *sel;        // [4 * 512]: per quadrant and stone mask, the selectors for k = 0..3
+    const uint16_t *chunk_ref;  // [4 * 18]
+    const uint32_t *u_ref;      // [4 * 15]
     const uint32_t *dag_node;   // all DAG layouts back to back (cmask | omask << 16)
     const uint16_t *dag_rank;   // all rank tables back to back
     int dag_node_off[11];       // start of layout e in dag_node
@@ -75,6 +78,8 @@ hipError_t launch_eval_group(const uint64_t *boards, int e, int first, int count
                              const EvalScratch &S, const DevTables &T, hipStream_t s);
 
 int dag_lds_bytes(int e);
+// Dynamic LDS of one sweep tile with G lines and child lines of cmD entries.
+int sweep_lds_bytes(int G, int cmD);
 
 // Nodes of the largest layer of any supported root (10 empty cells).
 constexpr int kDagGlobalLayer = 4200;

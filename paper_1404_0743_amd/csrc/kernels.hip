@@ -134,16 +134,138 @@ __device__ __forceinline__ Set256 lds_set(const uint4 *p)
     return x;
 }
 
+// ---------------------------------------------------------------------------
+// Five-in-a-row sets along a line (Section III five-sets, Section IV lines).
+//
+// Inside a tile every entry of one line shares the patterns of the three
+// quadrants other than D; only quadrant D varies.  The sweep works in an
+// internal layout where dimension D is exchanged with dimension 3, so for a
+// fixed turn k of quadrant D the five-set is one 64-bit word pair over the
+// other three dimensions:
+//   F[k] = U | OR over lines l through D that quadrant D completes at k of O_l
+// where U collects the lines missing D and O_l is the product of l's
+// cylinders in the other quadrants it touches.  The 17 lines through D are
+// split into the three chunks of quadrant D's LineMasks (6 slots each), and
+// each chunk gets a 64-entry table over subsets of its lines, so F[k] is
+// three table reads.  The selectors (which lines D completes at k) depend
+// only on D's pattern and come from T.sel.
+// ---------------------------------------------------------------------------
+
+// Cylinder over internal dimensions 0..2 (bit a0 + 4 a1 + 16 a2 of a word
+// pair): the elements whose coordinate p lies in the 4-bit set m.
+__device__ __forceinline__ uint2 cyl64(int p, uint32_t m)
+{
+    if (p == 0) {
+        uint32_t h = m * 0x1111u;
+        h |= h << 16;
+        return make_uint2(h, h);
+    }
+    if (p == 1) {
+        uint32_t h = fill_g1(m);
+        h |= h << 16;
+        return make_uint2(h, h);
+    }
+    const uint32_t lo = ((m & 1u) ? 0x0000ffffu : 0u) | ((m & 2u) ? 0xffff0000u : 0u);
+    const uint32_t hi = ((m & 4u) ? 0x0000ffffu : 0u) | ((m & 8u) ? 0xffff0000u : 0u);
+    return make_uint2(lo, hi);
+}
+
+// LDS layout of one tile, per line: LineMasks of the 4 quadrants for both
+// colours, the 19 partial sets (18 chunk lines + U) for both colours, and the
+// 3 x 64 chunk tables for both colours.  Child records follow (18 dwords each:
+// A then B in the internal layout, 2 dwords of padding against bank clashes).
+constexpr int kLmqBytes = 2 * 4 * 12;
+constexpr int kOBytes = 2 * 19 * 8;
+constexpr int kLutBytes = 2 * 3 * 64 * 8;
+constexpr int kLineBytes = kLmqBytes + kOBytes + kLutBytes;
+constexpr int kRecWords = 18;
+
+struct TileLds {
+    LineMasks *lmq;   // [G][2][4]
+    uint2 *O;         // [G][2][19]
+    uint2 *lut;       // [G][2][3][64]
+    uint32_t *rec;    // [G][cmD][18]
+};
+
+__device__ __forceinline__ TileLds tile_lds(void *base, int G)
+{
+    char *p = (char *)base;
+    TileLds L;
+    L.lut = (uint2 *)p;
+    p += G * kLutBytes;
+    L.O = (uint2 *)p;
+    p += G * kOBytes;
+    L.lmq = (LineMasks *)p;
+    p += G * kLmqBytes;
+    L.rec = (uint32_t *)p;
+    return L;
+}
+
+__device__ __forceinline__ uint32_t ref_mu(const LineMasks *lmq, uint32_t ref)
+{
+    const LineMasks L = lmq[ref & 3];
+    const uint32_t f = (ref >> 2) & 3;
+    const uint32_t fld = f == 0 ? L.a : f == 1 ? L.b : L.c;
+    return (fld >> (4 * (ref >> 4))) & 0xfu;
+}
+
+// internal position of quadrant j when D is exchanged with 3 (j != D)
+__device__ __forceinline__ int ipos(int j, int D) { return j == 3 ? D : j; }
+
+template <int D>
+__device__ __forceinline__ uint2 ref_product(const LineMasks *lmq, uint32_t refs, int nref)
+{
+    uint2 r = make_uint2(0xffffffffu, 0xffffffffu);
+    for (int i = 0; i < nref; i++) {
+        const uint32_t ref = (refs >> (8 * i)) & 0xffu;
+        if (ref == 0xffu) break;
+        const uint2 c = cyl64(ipos(ref & 3, D), ref_mu(lmq, ref));
+        r.x &= c.x;
+        r.y &= c.y;
+    }
+    return r;
+}
+
+// Five-set of a board of the line from the line's chunk tables and the
+// selectors of its quadrant-D pattern (internal layout).
+__device__ __forceinline__ Set256 five_lut(const uint2 *lut, const uint4 sel)
+{
+    Set256 F;
+    const uint32_t s4[4] = {sel.x, sel.y, sel.z, sel.w};
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const uint2 a = lut[s4[k] & 63u];
+        const uint2 b = lut[64 + ((s4[k] >> 6) & 63u)];
+        const uint2 c = lut[128 + ((s4[k] >> 12) & 63u)];
+        F.w[2 * k] = a.x | b.x | c.x;
+        F.w[2 * k + 1] = a.y | b.y | c.y;
+    }
+    return F;
+}
+
+// OR into acc the 8-word set at p shifted by k along internal dimension 3
+// (a re-addressing of the four word pairs).
+__device__ __forceinline__ void or_rotated(Set256 &acc, const uint32_t *p, int k)
+{
+#pragma unroll
+    for (int g3 = 0; g3 < 4; g3++) {
+        const uint2 v = *(const uint2 *)(p + 2 * ((g3 - k) & 3));
+        acc.w[2 * g3] |= v.x;
+        acc.w[2 * g3 + 1] |= v.y;
+    }
+}
+
 // Children of one parent along a dimension JD that is not staged: their
-// A/B terms were prepared per child entry by prep_kernel (64 B each, in the
-// child section's blocked layout).
-template <int JD>
+// A/B terms were prepared per child entry by prep_kernel, in the parent's
+// internal layout (64 B each, in the child section's blocked order).
+template <int D, int JD>
 __device__ __forceinline__ void direct_children(const SweepJob &J, const DevTables &T,
                                                 const Idx4 &idx, const QInfo &q, Set256 &Wnt,
                                                 Set256 &Nnt)
 {
     int cshape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
     cshape[JD] = J.cm[JD];
+    constexpr int ip = JD == 3 ? D : JD;
     unsigned empt = ~(unsigned)(q.bm | q.wm) & 0x1ffu;
     while (empt) {
         const int cell = __builtin_ctz(empt);
@@ -152,13 +274,14 @@ __device__ __forceinline__ void direct_children(const SweepJob &J, const DevTabl
         Idx4 cidx = idx;
         cidx.v[JD] = cc & 0xfff;
         const uint4 *p = J.prep[JD] + 4 * block_offset(cshape, cidx.v);
-        s_or_into(Wnt, shift_dim(lds_set(p), JD, cc >> 12));
-        s_or_into(Nnt, shift_dim(lds_set(p + 2), JD, cc >> 12));
+        s_or_into(Wnt, shift_dim(lds_set(p), ip, cc >> 12));
+        s_or_into(Nnt, shift_dim(lds_set(p + 2), ip, cc >> 12));
     }
 }
 
 // A/B terms of every entry of the child section along JD (for dimensions
-// that a sweep does not stage in LDS).
+// that a sweep does not stage in LDS), written in the internal layout of the
+// parent's sweep (dimension J.d exchanged with 3).
 template <int JD>
 __global__ void __launch_bounds__(256) prep_kernel(SweepJob J, DevTables T)
 {
@@ -175,6 +298,8 @@ __global__ void __launch_bounds__(256) prep_kernel(SweepJob J, DevTables T)
         idx.v[0] = (int)r;
         Set256 A, B;
         child_entry_terms<JD>(J, T, idx, A, B);
+        swap_with3_rt(A, J.d);
+        swap_with3_rt(B, J.d);
         uint4 *p = J.prep_out[JD] + 4 * block_offset(cshape, idx.v);
         p[0] = make_uint4(A.w[0], A.w[1], A.w[2], A.w[3]);
         p[1] = make_uint4(A.w[4], A.w[5], A.w[6], A.w[7]);
@@ -183,8 +308,10 @@ __global__ void __launch_bounds__(256) prep_kernel(SweepJob J, DevTables T)
     }
 }
 
+int sweep_lds_bytes(int G, int cmD) { return G * kLineBytes + G * cmD * kRecWords * 4; }
+
 template <int D>
-__device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile, uint4 *lds)
+__device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile, void *lds_base)
 {
     const int grp = (int)(tile % J.ngroups);
     const long long rest = tile / J.ngroups;
@@ -199,8 +326,54 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
     const int c = J.mover;
     const bool staged = (J.emask >> D) & 1;
     const int cmD = J.cm[D];
+    const TileLds L = tile_lds(lds_base, J.G);
 
-    // Phase 1: stage the child line(s) of dimension D (Fig. 3 "gather").
+    // Phase 0: per-line tables (LineMasks of the fixed quadrants, partial
+    // sets, chunk tables), for both colours.
+    for (int it = threadIdx.x; it < nlines * 8; it += blockDim.x) {
+        const int v = it >> 3, x = ((it >> 2) & 1) + 1, j = it & 3;
+        const int ij = get4(base, j) + (j == J.e ? v : 0);
+        const int qbj = j == 0 ? J.qb[0] : j == 1 ? J.qb[1] : j == 2 ? J.qb[2] : J.qb[3];
+        const QInfo q = T.qinfo[j == D ? 0 : qbj + ij];
+        const LineMasks lm = T.lm[j * 512 + (x == 1 ? q.bm : q.wm)];
+        const bool keep = j != D;
+        L.lmq[it] = LineMasks{keep ? lm.a : 0u, keep ? lm.b : 0u, keep ? lm.c : 0u};
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < nlines * 2 * 19; it += blockDim.x) {
+        const int vx = it / 19, slot = it % 19;
+        const LineMasks *lmq = L.lmq + 4 * vx;
+        uint2 r;
+        if (slot < 18) {
+            const uint32_t refs = T.chunk_ref[D * 18 + slot];
+            r = refs == 0xffffu ? make_uint2(0, 0) : ref_product<D>(lmq, refs, 2);
+        } else {
+            r = make_uint2(0, 0);
+            for (int l = 0; l < 15; l++) {
+                const uint2 p = ref_product<D>(lmq, T.u_ref[D * 15 + l], 3);
+                r.x |= p.x;
+                r.y |= p.y;
+            }
+        }
+        L.O[it] = r;
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < nlines * 2 * 3 * 64; it += blockDim.x) {
+        const int sigma = it & 63, ch = (it >> 6) % 3, vx = it / 192;
+        const uint2 *O = L.O + 19 * vx;
+        uint2 r = ch == 0 ? O[18] : make_uint2(0, 0);
+#pragma unroll
+        for (int b = 0; b < 6; b++)
+            if ((sigma >> b) & 1) {
+                r.x |= O[6 * ch + b].x;
+                r.y |= O[6 * ch + b].y;
+            }
+        L.lut[it] = r;
+    }
+    __syncthreads();
+
+    // Phase 1: stage the child line(s) of dimension D (Fig. 3 "gather"):
+    // A = F_c(child) | rmax(not N_child), B = F_c(child) | rmax(not W_child).
     if (staged) {
         const int total = nlines * cmD;
         for (int it = threadIdx.x; it < total; it += blockDim.x) {
@@ -215,16 +388,35 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
                 v = it % nlines;
                 ic = it / nlines;
             }
-            Idx4 idx = base;
-            set4(idx, J.e, get4(base, J.e) + v);
-            idx.v[D] = ic;
+            const QInfo q = T.qinfo[J.cqb[D] + ic];
+            const uint2 *lut = L.lut + 384 * v;
+            const Set256 Fc = five_lut(lut + 192 * (c - 1), T.sel[D * 512 + (c == 1 ? q.bm : q.wm)]);
+            Set256 W, N;
+            if ((J.odmask >> D) & 1) {
+                const Set256 Fo = five_lut(lut + 192 * (2 - c), T.sel[D * 512 + (c == 1 ? q.wm : q.bm)]);
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    W.w[i] = Fo.w[i] & ~Fc.w[i];
+                    N.w[i] = Fo.w[i] | ~Fc.w[i];
+                }
+            } else {
+                Idx4 idx = base;
+                set4(idx, J.e, get4(base, J.e) + v);
+                idx.v[D] = ic;
+                int cshape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
+                cshape[D] = cmD;
+                load_info(J.child[D] + 4 * block_offset(cshape, idx.v), W, N);
+                swap_with3<D>(W);
+                swap_with3<D>(N);
+            }
             Set256 A, B;
-            child_entry_terms<D>(J, T, idx, A, B);
-            uint4 *p = lds + 4 * (v * cmD + ic);
-            p[0] = make_uint4(A.w[0], A.w[1], A.w[2], A.w[3]);
-            p[1] = make_uint4(A.w[4], A.w[5], A.w[6], A.w[7]);
-            p[2] = make_uint4(B.w[0], B.w[1], B.w[2], B.w[3]);
-            p[3] = make_uint4(B.w[4], B.w[5], B.w[6], B.w[7]);
+            child_terms(Fc, W, N, A, B);
+            uint32_t *r = L.rec + kRecWords * (v * cmD + ic);
+#pragma unroll
+            for (int i = 0; i < 8; i += 2) {
+                *(uint2 *)(r + i) = make_uint2(A.w[i], A.w[i + 1]);
+                *(uint2 *)(r + 8 + i) = make_uint2(B.w[i], B.w[i + 1]);
+            }
         }
         __syncthreads();
     }
@@ -248,43 +440,41 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
         Idx4 idx = base;
         set4(idx, J.e, get4(base, J.e) + v);
         idx.v[D] = iD;
-
-        QInfo q[4];
-#pragma unroll
-        for (int j = 0; j < 4; j++) q[j] = T.qinfo[J.qb[j] + idx.v[j]];
+        const QInfo qD = T.qinfo[J.qb[D] + iD];
 
         Set256 Wnt = s_zero(), Nnt = s_zero();
         if (J.emask == 0) Nnt = s_full();
         if (staged) {
-            unsigned empt = ~(unsigned)(q[D].bm | q[D].wm) & 0x1ffu;
-            const uint4 *line = lds + 4 * (v * cmD);
+            unsigned empt = ~(unsigned)(qD.bm | qD.wm) & 0x1ffu;
+            const uint32_t *line = L.rec + kRecWords * (v * cmD);
             while (empt) {
                 const int cell = __builtin_ctz(empt);
                 empt &= empt - 1;
-                const uint16_t cc = T.canon[q[D].code + c * c_pow3[cell]];
-                const int ic = cc & 0xfff, k = cc >> 12;
-                const uint4 *p = line + 4 * ic;
-                s_or_into(Wnt, shift_dim(lds_set(p), D, k));
-                s_or_into(Nnt, shift_dim(lds_set(p + 2), D, k));
+                const uint16_t cc = T.canon[qD.code + c * c_pow3[cell]];
+                const uint32_t *r = line + kRecWords * (cc & 0xfff);
+                or_rotated(Wnt, r, cc >> 12);
+                or_rotated(Nnt, r + 8, cc >> 12);
             }
         }
         // Children along the other dimensions with empty cells.
-        if (D != 0 && (J.emask & 1)) direct_children<0>(J, T, idx, q[0], Wnt, Nnt);
-        if (D != 1 && (J.emask & 2)) direct_children<1>(J, T, idx, q[1], Wnt, Nnt);
-        if (D != 2 && (J.emask & 4)) direct_children<2>(J, T, idx, q[2], Wnt, Nnt);
-        if (D != 3 && (J.emask & 8)) direct_children<3>(J, T, idx, q[3], Wnt, Nnt);
-
-        unsigned cm_[4], om_[4];
+        if (J.emask & ~(1 << D)) {
+            QInfo q[4];
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            cm_[j] = c == 1 ? q[j].bm : q[j].wm;
-            om_[j] = c == 1 ? q[j].wm : q[j].bm;
+            for (int j = 0; j < 4; j++) q[j] = T.qinfo[J.qb[j] + idx.v[j]];
+            if (D != 0 && (J.emask & 1)) direct_children<D, 0>(J, T, idx, q[0], Wnt, Nnt);
+            if (D != 1 && (J.emask & 2)) direct_children<D, 1>(J, T, idx, q[1], Wnt, Nnt);
+            if (D != 2 && (J.emask & 4)) direct_children<D, 2>(J, T, idx, q[2], Wnt, Nnt);
+            if (D != 3 && (J.emask & 8)) direct_children<D, 3>(J, T, idx, q[3], Wnt, Nnt);
         }
-        const Set256 Fc = board_five(T, cm_);
-        const Set256 Fo = board_five(T, om_);
+        const uint2 *lut = L.lut + 384 * v;
+        const Set256 Fc = five_lut(lut + 192 * (c - 1), T.sel[D * 512 + (c == 1 ? qD.bm : qD.wm)]);
+        const Set256 Fo = five_lut(lut + 192 * (2 - c), T.sel[D * 512 + (c == 1 ? qD.wm : qD.bm)]);
         Set256 W, N;
         combine(Fc, Fo, Wnt, Nnt, W, N);
-        store_info(J.out + 4 * block_offset(J.m, idx.v), W, N);
+        swap_with3<D>(W);
+        swap_with3<D>(N);
+        const int shape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
+        store_info(J.out + 4 * block_offset(shape, idx.v), W, N);
     }
 }
 
@@ -292,7 +482,7 @@ template <int D>
 __global__ void __launch_bounds__(256) sweep_kernel(SweepJob J, DevTables T)
 {
     extern __shared__ uint4 lds[];
-    sweep_tile<D>(J, T, blockIdx.x, lds);
+    sweep_tile<D>(J, T, blockIdx.x, (void *)lds);
 }
 
 // Many sections in one persistent launch: workgroups take tiles from a
@@ -318,10 +508,10 @@ __global__ void __launch_bounds__(256)
         const SweepJob &J = jobs[lo];
         const long long local = t - tile_start[lo];
         switch (J.d) {
-        case 0: sweep_tile<0>(J, T, local, lds); break;
-        case 1: sweep_tile<1>(J, T, local, lds); break;
-        case 2: sweep_tile<2>(J, T, local, lds); break;
-        default: sweep_tile<3>(J, T, local, lds); break;
+        case 0: sweep_tile<0>(J, T, local, (void *)lds); break;
+        case 1: sweep_tile<1>(J, T, local, (void *)lds); break;
+        case 2: sweep_tile<2>(J, T, local, (void *)lds); break;
+        default: sweep_tile<3>(J, T, local, (void *)lds); break;
         }
         __syncthreads();
     }

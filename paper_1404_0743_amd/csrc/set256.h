@@ -52,6 +52,12 @@ PG_HD Set256 s_not(const Set256 &a)
 
 PG_HD uint32_t rotr32(uint32_t x, int s) { return (x >> s) | (x << (32 - s)); }
 
+// (m & a) | (~m & b): one v_bfi_b32
+PG_HD uint32_t bfi(uint32_t m, uint32_t a, uint32_t b) { return (m & a) | (~m & b); }
+
+// swap the two bytes of each 16-bit half
+PG_HD uint32_t swap_bytes16(uint32_t x) { return ((x >> 8) & 0x00ff00ffu) | ((x << 8) & 0xff00ff00u); }
+
 // rmax(X)(g) = OR over the 8 single-quadrant turns r of X(g + r) (Section III).
 // Along each dimension the two neighbours g_j +- 1 of g_j are the two values
 // of the other parity, so each dimension costs a pair-swap plus an OR.
@@ -61,19 +67,23 @@ PG_HD Set256 rmax(const Set256 &x)
     uint32_t n2[4];
 #pragma unroll
     for (int g3 = 0; g3 < 4; g3++) n2[g3] = rotr32(x.w[2 * g3] | x.w[2 * g3 + 1], 16);
+    uint32_t n3[4];
+#pragma unroll
+    for (int p = 0; p < 2; p++) {
+        n3[p] = x.w[2 + p] | x.w[6 + p];      // neighbours of g3 = 0 and 2
+        n3[2 + p] = x.w[0 + p] | x.w[4 + p];  // neighbours of g3 = 1 and 3
+    }
 #pragma unroll
     for (int w = 0; w < 8; w++) {
         const int g3 = w >> 1, p = w & 1;
         const uint32_t u = x.w[w];
         // dimension 0: bits inside nibbles
-        uint32_t y0 = u | (((u >> 2) & 0x33333333u) | ((u << 2) & 0xccccccccu));
-        uint32_t n0 = ((y0 >> 1) & 0x55555555u) | ((y0 << 1) & 0xaaaaaaaau);
+        const uint32_t y0 = u | bfi(0x33333333u, u >> 2, u << 2);
+        const uint32_t n0 = bfi(0x55555555u, y0 >> 1, y0 << 1);
         // dimension 1: nibbles inside halves
-        uint32_t y1 = u | (((u >> 8) & 0x00ff00ffu) | ((u << 8) & 0xff00ff00u));
-        uint32_t n1 = ((y1 >> 4) & 0x0f0f0f0fu) | ((y1 << 4) & 0xf0f0f0f0u);
-        // dimension 3: word pairs
-        uint32_t n3 = x.w[2 * ((g3 + 1) & 3) + p] | x.w[2 * ((g3 + 3) & 3) + p];
-        r.w[w] = n0 | n1 | n2[g3] | n3;
+        const uint32_t y1 = u | swap_bytes16(u);
+        const uint32_t n1 = bfi(0x0f0f0f0fu, y1 >> 4, y1 << 4);
+        r.w[w] = n0 | n1 | n2[g3] | n3[(g3 & 1) * 2 + p];
     }
     return r;
 }
@@ -121,6 +131,53 @@ PG_HD Set256 shift_dim(const Set256 &x, int d, int k)
         for (int w = 0; w < 8; w++) r.w[w] = (k & 2) ? t[(w + 4) & 7] : t[w];
     }
     return r;
+}
+
+// Exchange index bit I (inside a word, I < 5) with word-index bit B: the
+// elements whose bit I is 1 and bit B is 0 trade places with those whose bit
+// I is 0 and bit B is 1.
+template <int I, int B>
+PG_HD void swap_index_bits(Set256 &x)
+{
+    constexpr int s = 1 << I;
+    constexpr uint32_t M = I == 0 ? 0x55555555u : I == 1 ? 0x33333333u : I == 2 ? 0x0f0f0f0fu
+                         : I == 3 ? 0x00ff00ffu : 0x0000ffffu;
+#pragma unroll
+    for (int w = 0; w < 8; w++) {
+        if ((w >> B) & 1) continue;
+        const int w2 = w | (1 << B);
+        const uint32_t t = ((x.w[w] >> s) ^ x.w[w2]) & M;
+        x.w[w2] ^= t;
+        x.w[w] ^= t << s;
+    }
+}
+
+// Exchange dimensions D and 3 of L (self-inverse).  The sweep keeps the
+// dimension of the quadrant that receives stones in the word-pair position,
+// where a cyclic shift along it is a re-addressing of word pairs.
+template <int D>
+PG_HD void swap_with3(Set256 &x)
+{
+    if (D == 3) return;
+    if (D == 2) {
+        // index bit 4 (half) <-> bit 6 (word bit 1); bit 5 (word bit 0) <-> bit 7 (word bit 2)
+        swap_index_bits<4, 1>(x);
+        uint32_t t = x.w[1]; x.w[1] = x.w[4]; x.w[4] = t;
+        t = x.w[3]; x.w[3] = x.w[6]; x.w[6] = t;
+    } else {
+        swap_index_bits<2 * D, 1>(x);
+        swap_index_bits<2 * D + 1, 2>(x);
+    }
+}
+
+PG_HD void swap_with3_rt(Set256 &x, int D)
+{
+    switch (D) {
+    case 0: swap_with3<0>(x); break;
+    case 1: swap_with3<1>(x); break;
+    case 2: swap_with3<2>(x); break;
+    default: break;
+    }
 }
 
 // ------------------------------------------------------------------------

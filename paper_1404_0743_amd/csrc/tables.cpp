@@ -86,6 +86,21 @@ static std::vector<LineDef> all_lines()
     return out;
 }
 
+// Field and nibble in which quadrant q keeps line d (layout at LineMasks).
+static void line_slot(const LineDef &d, int *field, int *pos)
+{
+    if (d.group < 4) {
+        *field = (d.group == 0 || d.group == 1) ? 0 : 1;
+        *pos = d.slot;
+    } else if (d.group < 6) {
+        *field = 2;
+        *pos = d.slot;
+    } else {
+        *field = 2;
+        *pos = 2 + d.slot;
+    }
+}
+
 static void build_line_masks(HostTables &t)
 {
     t.lm.assign(4 * 512, LineMasks{0, 0, 0});
@@ -100,17 +115,7 @@ static void build_line_masks(HostTables &t)
             if (!cells) continue;
             // which field/nibble of quadrant q's record holds this line
             int field, pos;
-            if (d.group < 4) {
-                const bool first = (d.group == 0 || d.group == 1);  // rows are field a
-                field = first ? 0 : 1;
-                pos = d.slot;
-            } else if (d.group < 6) {
-                field = 2;
-                pos = d.slot;
-            } else {
-                field = 2;
-                pos = 2 + d.slot;
-            }
+            line_slot(d, &field, &pos);
             for (unsigned m = 0; m < 512; m++) {
                 unsigned mu = 0;
                 for (int k = 0; k < 4; k++)
@@ -119,6 +124,54 @@ static void build_line_masks(HostTables &t)
                 uint32_t &f = field == 0 ? rec.a : field == 1 ? rec.b : rec.c;
                 f |= mu << (4 * pos);
             }
+        }
+    }
+}
+
+static int line_quadrants(const LineDef &d)
+{
+    int m = 0;
+    for (int i = 0; i < 5; i++) {
+        const int r = d.cells[i] / 6, c = d.cells[i] % 6;
+        m |= 1 << (2 * (r / 3) + c / 3);
+    }
+    return m;
+}
+
+static void build_line_structure(HostTables &t)
+{
+    t.sel.assign(4 * 512 * 4, 0);
+    for (int j = 0; j < 4; j++)
+        for (int m = 0; m < 512; m++) {
+            const LineMasks &L = t.lm[j * 512 + m];
+            const uint32_t f[3] = {L.a, L.b, L.c};
+            for (int k = 0; k < 4; k++) {
+                uint32_t v = 0;
+                for (int ff = 0; ff < 3; ff++)
+                    for (int sl = 0; sl < 6; sl++)
+                        if ((f[ff] >> (4 * sl + k)) & 1) v |= 1u << (6 * ff + sl);
+                t.sel[(j * 512 + m) * 4 + k] = v;
+            }
+        }
+    t.chunk_ref.assign(4 * 18, 0xffff);
+    t.u_ref.assign(4 * 15, 0xffffffffu);
+    const std::vector<LineDef> lines = all_lines();
+    for (int D = 0; D < 4; D++) {
+        int nu = 0;
+        for (const LineDef &d : lines) {
+            const int qm = line_quadrants(d);
+            int field, pos;
+            line_slot(d, &field, &pos);
+            uint32_t refs = 0xffffffffu;
+            int nr = 0;
+            for (int j = 0; j < 4; j++) {
+                if (!((qm >> j) & 1) || j == D) continue;
+                const uint32_t ref = (uint32_t)(j | (field << 2) | (pos << 4));
+                refs = (refs & ~(0xffu << (8 * nr))) | (ref << (8 * nr));
+                nr++;
+            }
+            if ((qm >> D) & 1) t.chunk_ref[D * 18 + 6 * field + pos] = (uint16_t)(refs & 0xffff);
+            else t.u_ref[D * 15 + nu++] = refs;
         }
     }
 }
@@ -166,6 +219,7 @@ static void build(HostTables &t)
     for (int code = 0; code < NC; code++)
         t.canon[code] = (uint16_t)(index[minc[code]] | (mink[code] << 12));
     build_line_masks(t);
+    build_line_structure(t);
 }
 
 const HostTables &host_tables()

@@ -26,6 +26,20 @@ struct HostTables {
                                   // its class representative
     std::vector<uint16_t> turn1;  // per code: code after one counter-clockwise turn
     std::vector<LineMasks> lm;    // [quadrant * 512 + stone mask]
+
+    // Line structure used by the sweep (see LineSelect in kernels.h):
+    // sel[j * 512 + m] holds, for k = 0..3, the 18-bit selector of the lines
+    // through quadrant j that its pattern m completes after k turns: bit s of
+    // chunk f (6 bits each, f = fields a, b, c of LineMasks) set iff nibble s
+    // of field f of lm[j*512+m] contains k.
+    std::vector<uint32_t> sel;    // [4 * 512 * 4]
+    // chunk_ref[D * 18 + 6f + s]: the other quadrants of the line kept in
+    // nibble s of field f of quadrant D's LineMasks, as up to two refs
+    // (quadrant | field << 2 | nibble << 4), 0xff = none.
+    std::vector<uint16_t> chunk_ref;  // [4 * 18]
+    // u_ref[D * 15 + i]: the 15 lines that miss quadrant D, each as up to
+    // three refs (byte per ref, 0xff = none).
+    std::vector<uint32_t> u_ref;      // [4 * 15]
 };
 
 // Built once on first use (thread-safe).

@@ -75,6 +75,7 @@ _SIGS = {
     "pentago_debug_rmax": ([_P, _P], ctypes.c_int),
     "pentago_debug_shift": ([_P, ctypes.c_int, ctypes.c_int, _P], ctypes.c_int),
     "pentago_debug_canon": ([ctypes.c_int, _P, _P], ctypes.c_int),
+    "pentago_debug_swap3": ([_P, ctypes.c_int, _P], ctypes.c_int),
 }
 
 
@@ -292,6 +293,12 @@ def pentago_debug_shift(words, d, k):
     src, out = _set(words), Set256()
     _check(lib().pentago_debug_shift(ctypes.byref(src), d, k, ctypes.byref(out)),
            "pentago_debug_shift")
+    return np.array(out.w, dtype=np.uint64)
+
+
+def pentago_debug_swap3(words, d):
+    src, out = _set(words), Set256()
+    _check(lib().pentago_debug_swap3(ctypes.byref(src), d, ctypes.byref(out)), "pentago_debug_swap3")
     return np.array(out.w, dtype=np.uint64)
 
 

@@ -119,3 +119,17 @@ def test_canon_matches_oracle():
         idx, kk = P.pentago_debug_canon(code)
         assert kk == k
         assert O.class_codes(b, w)[idx] == m
+
+
+def test_swap3_matches_definition():
+    rng = np.random.default_rng(8)
+    for _ in range(20):
+        x = rng.random(256) < 0.5
+        for d in range(4):
+            got = bits_of(P.pentago_debug_swap3(words_of(x), d))
+            want = np.zeros(256, bool)
+            for g in range(256):
+                c = [(g >> (2 * j)) & 3 for j in range(4)]
+                c[d], c[3] = c[3], c[d]
+                want[sum(c[j] << (2 * j) for j in range(4))] = x[g]
+            assert np.array_equal(got, want)
