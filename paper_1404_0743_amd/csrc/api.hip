@@ -197,6 +197,11 @@ int make_job(const pentago_section &s, const pentago_superinfo *const child[4],
             best_cm = J->cm[j];
         }
     }
+    {
+        uint64_t entries = 1;
+        for (int j = 0; j < 4; j++) entries *= (uint64_t)J->m[j];
+        if (entries >= (1ull << 32)) return fail(PENTAGO_ERANGE, "sections of 2^32 entries or more are not supported");
+    }
     if (force_d >= 0 && ((J->emask >> force_d) & 1)) best = force_d;
     J->d = best >= 0 ? best : 3;
     J->e = J->d == 3 ? 2 : 3;
@@ -206,14 +211,21 @@ int make_job(const pentago_section &s, const pentago_superinfo *const child[4],
     J->o1 = o[0];
     J->o2 = o[1];
     const int cmd = (J->emask >> J->d) & 1 ? J->cm[J->d] : 0;
+    // lines per tile: at most 8 (one 8^4 block row), the child items of a
+    // tile in one pass of its 256 threads when the child line allows, and the
+    // tile's LDS within 64 KiB
     int G = 8;
     if (forceG > 0) G = forceG;
-    else
-        while (G > 1 && sweep_lds_bytes(G, cmd) > 65536) G >>= 1;
+    else if (int tuned = tuned_tile_lines(*J)) G = tuned;
+    else {
+        // (the kernels give every line 8 slots per position when D == 3,
+        // so a smaller G only helps the child pass for D == 3)
+        while (G > 1 && sweep_lds_bytes(G, J->m[J->d], cmd) > 65536) G--;
+    }
     J->G = G;
     J->ngroups = (J->m[J->e] + G - 1) / G;
     J->ntiles = (long long)J->m[J->o1] * J->m[J->o2] * J->ngroups;
-    J->lds_bytes = sweep_lds_bytes(G, cmd);
+    J->lds_bytes = sweep_lds_bytes(G, J->m[J->d], cmd);
     J->out = (uint4 *)out;
     return 0;
 }
@@ -295,21 +307,7 @@ int pentago_solve_section(pentago_section s, const pentago_superinfo *const chil
     SweepJob J;
     rc = make_job(s, child, out, &J, -1, 0);
     if (rc) return rc;
-    const hipStream_t st = (hipStream_t)hip_stream;
-    void *prep[4] = {nullptr, nullptr, nullptr, nullptr};
-    hipError_t e = hipSuccess;
-    for (int j = 0; j < 4 && e == hipSuccess; j++) {
-        if (j == J.d || !((J.emask >> j) & 1)) continue;
-        e = hipMallocAsync(&prep[j], prep_bytes(J, j), st);
-        if (e != hipSuccess) break;
-        J.prep[j] = J.prep_out[j] = (uint4 *)prep[j];
-        e = launch_prep(J, j, T, st);
-    }
-    if (e == hipSuccess) e = launch_sweep(J, T, st);
-    for (int j = 0; j < 4; j++)
-        if (prep[j]) (void)hipFreeAsync(prep[j], st);
-    if (e != hipSuccess) return hip_fail(e, "sweep launch");
-    return 0;
+    return run_job(J, T, (hipStream_t)hip_stream);
 }
 
 const char *pentago_strerror(int code)

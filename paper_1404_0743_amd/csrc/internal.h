@@ -22,5 +22,8 @@ uint64_t host_block_offset(const int *m, const int *idx);
 int make_job(const pentago_section &s, const pentago_superinfo *const child[4],
              pentago_superinfo *out, SweepJob *J, int force_d, int forceG);
 size_t prep_bytes(const SweepJob &J, int j);
+int run_job(SweepJob &J, const DevTables &T, hipStream_t st);
+int tuned_tile_lines(const SweepJob &J);
+void remember_tile_lines(const SweepJob &J, int G);
 
 }  // namespace pg

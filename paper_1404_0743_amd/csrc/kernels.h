@@ -78,8 +78,9 @@ hipError_t launch_eval_group(const uint64_t *boards, int e, int first, int count
                              const EvalScratch &S, const DevTables &T, hipStream_t s);
 
 int dag_lds_bytes(int e);
-// Dynamic LDS of one sweep tile with G lines and child lines of cmD entries.
-int sweep_lds_bytes(int G, int cmD);
+// Dynamic LDS of one sweep tile: G lines of mD parents, child lines of cmD
+// entries (cmD = 0 when the staged dimension has no children).
+int sweep_lds_bytes(int G, int mD, int cmD);
 
 // Nodes of the largest layer of any supported root (10 empty cells).
 constexpr int kDagGlobalLayer = 4200;

@@ -16,21 +16,23 @@ namespace pg {
 
 __constant__ uint32_t c_pow3[10] = {1, 3, 9, 27, 81, 243, 729, 2187, 6561, 19683};
 
-__device__ __forceinline__ uint64_t block_offset(const int *m, const int *idx)
+// Entry offset in the 8^4-blocked layout (see pentago_section_offset).  The
+// host rejects sections of 2^32 entries or more, so 32-bit arithmetic holds.
+__device__ __forceinline__ uint32_t block_offset(const int *m, const int *idx)
 {
-    int B[4], r[4], s[4];
+    uint32_t B[4], r[4], s[4];
 #pragma unroll
     for (int j = 0; j < 4; j++) {
-        B[j] = idx[j] >> 3;
-        r[j] = idx[j] & 7;
-        s[j] = min(8, m[j] - 8 * B[j]);
+        B[j] = (uint32_t)idx[j] >> 3;
+        r[j] = (uint32_t)idx[j] & 7u;
+        s[j] = min(8u, (uint32_t)m[j] - 8u * B[j]);
     }
-    const uint64_t m23 = (uint64_t)(m[2] * m[3]);
-    uint64_t off = (uint64_t)(8 * B[0]) * (uint64_t)m[1] * m23;
-    off += (uint64_t)(s[0] * 8 * B[1]) * m23;
-    off += (uint64_t)(s[0] * s[1] * 8 * B[2]) * (uint64_t)m[3];
-    off += (uint64_t)(s[0] * s[1] * s[2] * 8 * B[3]);
-    off += (uint64_t)(((r[0] * s[1] + r[1]) * s[2] + r[2]) * s[3] + r[3]);
+    const uint32_t m23 = (uint32_t)m[2] * (uint32_t)m[3];
+    uint32_t off = 8u * B[0] * (uint32_t)m[1] * m23;
+    off += s[0] * 8u * B[1] * m23;
+    off += s[0] * s[1] * 8u * B[2] * (uint32_t)m[3];
+    off += s[0] * s[1] * s[2] * 8u * B[3];
+    off += ((r[0] * s[1] + r[1]) * s[2] + r[2]) * s[3] + r[3];
     return off;
 }
 
@@ -175,22 +177,42 @@ __device__ __forceinline__ uint2 cyl64(int p, uint32_t m)
 // 3 x 64 chunk tables for both colours.  Child records follow (18 dwords each:
 // A then B in the internal layout, 2 dwords of padding against bank clashes).
 constexpr int kLmqBytes = 2 * 4 * 12;
-constexpr int kOBytes = 2 * 19 * 8;
-constexpr int kLutBytes = 2 * 3 * 64 * 8;
+constexpr int kOSlots = 22;                    // 18 chunk lines + U in 4 parts
+constexpr int kOBytes = 2 * kOSlots * 8;
+constexpr int kLutStride = 2 * 3 * 64 + 1;    // uint2 per line; +1 staggers the banks of lines
+constexpr int kLutBytes = kLutStride * 8;
 constexpr int kLineBytes = kLmqBytes + kOBytes + kLutBytes;
 constexpr int kRecWords = 18;
 
+// Per position along D (shared by every line of the tile): the selectors of
+// the pattern for both colours and, for a parent position, its children as
+// (child index | k << 12) per empty cell.
+struct PosRec {
+    uint4 sel_c, sel_o;
+    uint16_t nchild, child[9];
+    uint32_t pad[3];
+};
+struct ChildPosRec {
+    uint4 sel_c, sel_o;
+};
+
 struct TileLds {
     LineMasks *lmq;   // [G][2][4]
-    uint2 *O;         // [G][2][19]
-    uint2 *lut;       // [G][2][3][64]
+    uint2 *O;         // [G][2][kOSlots]
+    uint2 *lut;       // [G][kLutStride]
+    PosRec *pos;      // [mD]
+    ChildPosRec *cpos;  // [cmD]
     uint32_t *rec;    // [G][cmD][18]
 };
 
-__device__ __forceinline__ TileLds tile_lds(void *base, int G)
+__device__ __forceinline__ TileLds tile_lds(void *base, int G, int mD, int cmD)
 {
     char *p = (char *)base;
     TileLds L;
+    L.pos = (PosRec *)p;
+    p += mD * sizeof(PosRec);
+    L.cpos = (ChildPosRec *)p;
+    p += cmD * sizeof(ChildPosRec);
     L.lut = (uint2 *)p;
     p += G * kLutBytes;
     L.O = (uint2 *)p;
@@ -232,11 +254,12 @@ __device__ __forceinline__ Set256 five_lut(const uint2 *lut, const uint4 sel)
 {
     Set256 F;
     const uint32_t s4[4] = {sel.x, sel.y, sel.z, sel.w};
+    const char *base = (const char *)lut;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-        const uint2 a = lut[s4[k] & 63u];
-        const uint2 b = lut[64 + ((s4[k] >> 6) & 63u)];
-        const uint2 c = lut[128 + ((s4[k] >> 12) & 63u)];
+        const uint2 a = *(const uint2 *)(base + (s4[k] & 1023u));
+        const uint2 b = *(const uint2 *)(base + ((s4[k] >> 10) & 1023u));
+        const uint2 c = *(const uint2 *)(base + (s4[k] >> 20));
         F.w[2 * k] = a.x | b.x | c.x;
         F.w[2 * k + 1] = a.y | b.y | c.y;
     }
@@ -308,7 +331,11 @@ __global__ void __launch_bounds__(256) prep_kernel(SweepJob J, DevTables T)
     }
 }
 
-int sweep_lds_bytes(int G, int cmD) { return G * kLineBytes + G * cmD * kRecWords * 4; }
+int sweep_lds_bytes(int G, int mD, int cmD)
+{
+    return (int)(mD * sizeof(PosRec) + cmD * sizeof(ChildPosRec)) + G * kLineBytes +
+           G * cmD * kRecWords * 4;
+}
 
 template <int D>
 __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile, void *lds_base)
@@ -326,10 +353,13 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
     const int c = J.mover;
     const bool staged = (J.emask >> D) & 1;
     const int cmD = J.cm[D];
-    const TileLds L = tile_lds(lds_base, J.G);
+    const int mD = J.m[D];
+    const TileLds L = tile_lds(lds_base, J.G, mD, staged ? cmD : 0);
 
     // Phase 0: per-line tables (LineMasks of the fixed quadrants, partial
-    // sets, chunk tables), for both colours.
+    // sets, chunk tables), for both colours.  Work items are kept small and
+    // even: 8 per line for the masks, 44 per line for the partial sets (the
+    // 15 lines that miss D are split in 4 parts), 24 per line for the tables.
     for (int it = threadIdx.x; it < nlines * 8; it += blockDim.x) {
         const int v = it >> 3, x = ((it >> 2) & 1) + 1, j = it & 3;
         const int ij = get4(base, j) + (j == J.e ? v : 0);
@@ -339,9 +369,34 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
         const bool keep = j != D;
         L.lmq[it] = LineMasks{keep ? lm.a : 0u, keep ? lm.b : 0u, keep ? lm.c : 0u};
     }
+    // positions along D, resolved once for all lines of the tile
+    const int npos = mD + (staged ? cmD : 0);
+    for (int it = threadIdx.x; it < npos; it += blockDim.x) {
+        if (it < mD) {
+            const QInfo q = T.qinfo[J.qb[D] + it];
+            PosRec &r = L.pos[it];
+            const unsigned mc = c == 1 ? q.bm : q.wm, mo = c == 1 ? q.wm : q.bm;
+            r.sel_c = T.sel[D * 512 + mc];
+            r.sel_o = T.sel[D * 512 + mo];
+            unsigned empt = staged ? ~(unsigned)(q.bm | q.wm) & 0x1ffu : 0u;
+            int n = 0;
+            while (empt) {
+                const int cell = __builtin_ctz(empt);
+                empt &= empt - 1;
+                r.child[n++] = T.canon[q.code + c * c_pow3[cell]];
+            }
+            r.nchild = (uint16_t)n;
+        } else {
+            const QInfo q = T.qinfo[J.cqb[D] + (it - mD)];
+            const unsigned mc = c == 1 ? q.bm : q.wm, mo = c == 1 ? q.wm : q.bm;
+            ChildPosRec &cr = L.cpos[it - mD];
+            cr.sel_c = T.sel[D * 512 + mc];
+            cr.sel_o = T.sel[D * 512 + mo];
+        }
+    }
     __syncthreads();
-    for (int it = threadIdx.x; it < nlines * 2 * 19; it += blockDim.x) {
-        const int vx = it / 19, slot = it % 19;
+    for (int it = threadIdx.x; it < nlines * 2 * kOSlots; it += blockDim.x) {
+        const int vx = it / kOSlots, slot = it % kOSlots;
         const LineMasks *lmq = L.lmq + 4 * vx;
         uint2 r;
         if (slot < 18) {
@@ -349,7 +404,7 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
             r = refs == 0xffffu ? make_uint2(0, 0) : ref_product<D>(lmq, refs, 2);
         } else {
             r = make_uint2(0, 0);
-            for (int l = 0; l < 15; l++) {
+            for (int l = slot - 18; l < 15; l += 4) {
                 const uint2 p = ref_product<D>(lmq, T.u_ref[D * 15 + l], 3);
                 r.x |= p.x;
                 r.y |= p.y;
@@ -358,42 +413,50 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
         L.O[it] = r;
     }
     __syncthreads();
-    for (int it = threadIdx.x; it < nlines * 2 * 3 * 64; it += blockDim.x) {
-        const int sigma = it & 63, ch = (it >> 6) % 3, vx = it / 192;
-        const uint2 *O = L.O + 19 * vx;
-        uint2 r = ch == 0 ? O[18] : make_uint2(0, 0);
+    // chunk tables: item (line, colour, chunk, quarter) writes 16 entries
+    for (int it = threadIdx.x; it < nlines * 2 * 3 * 4; it += blockDim.x) {
+        const int qq = it & 3, ch = (it >> 2) % 3, vx = it / 12;
+        const uint2 *O = L.O + kOSlots * vx + 6 * ch;
+        uint2 o[6];
 #pragma unroll
-        for (int b = 0; b < 6; b++)
-            if ((sigma >> b) & 1) {
-                r.x |= O[6 * ch + b].x;
-                r.y |= O[6 * ch + b].y;
-            }
-        L.lut[it] = r;
+        for (int b = 0; b < 6; b++) o[b] = O[b];
+        uint2 base = make_uint2(0, 0);
+        if (ch == 0) {
+            const uint2 *U = L.O + kOSlots * vx + 18;
+            base.x = U[0].x | U[1].x | U[2].x | U[3].x;
+            base.y = U[0].y | U[1].y | U[2].y | U[3].y;
+        }
+        if (qq & 1) { base.x |= o[4].x; base.y |= o[4].y; }
+        if (qq & 2) { base.x |= o[5].x; base.y |= o[5].y; }
+        uint2 *dst = L.lut + kLutStride * (vx >> 1) + 192 * (vx & 1) + 64 * ch + 16 * qq;
+#pragma unroll
+        for (int t = 0; t < 16; t++) {
+            uint2 r = base;
+            if (t & 1) { r.x |= o[0].x; r.y |= o[0].y; }
+            if (t & 2) { r.x |= o[1].x; r.y |= o[1].y; }
+            if (t & 4) { r.x |= o[2].x; r.y |= o[2].y; }
+            if (t & 8) { r.x |= o[3].x; r.y |= o[3].y; }
+            dst[t] = r;
+        }
     }
     __syncthreads();
 
     // Phase 1: stage the child line(s) of dimension D (Fig. 3 "gather"):
     // A = F_c(child) | rmax(not N_child), B = F_c(child) | rmax(not W_child).
     if (staged) {
+        // item it -> (child position ic, line v): it / nlines by a 16-bit
+        // reciprocal, exact for it < 8 * 420 and nlines <= 8
         const int total = nlines * cmD;
+        const uint32_t rcp = (65536u + nlines - 1) / nlines;
         for (int it = threadIdx.x; it < total; it += blockDim.x) {
-            int v, ic;
-            if (D == 3) {
-                const int B3 = it / (8 * nlines);
-                const int rem = it - B3 * 8 * nlines;
-                const int s3 = min(8, cmD - 8 * B3);
-                v = rem / s3;
-                ic = 8 * B3 + rem % s3;
-            } else {
-                v = it % nlines;
-                ic = it / nlines;
-            }
-            const QInfo q = T.qinfo[J.cqb[D] + ic];
-            const uint2 *lut = L.lut + 384 * v;
-            const Set256 Fc = five_lut(lut + 192 * (c - 1), T.sel[D * 512 + (c == 1 ? q.bm : q.wm)]);
+            const int ic = (int)(((uint32_t)it * rcp) >> 16);
+            const int v = it - ic * nlines;
+            const ChildPosRec cp = L.cpos[ic];
+            const uint2 *lut = L.lut + kLutStride * v;
+            const Set256 Fc = five_lut(lut + 192 * (c - 1), cp.sel_c);
             Set256 W, N;
             if ((J.odmask >> D) & 1) {
-                const Set256 Fo = five_lut(lut + 192 * (2 - c), T.sel[D * 512 + (c == 1 ? q.wm : q.bm)]);
+                const Set256 Fo = five_lut(lut + 192 * (2 - c), cp.sel_o);
 #pragma unroll
                 for (int i = 0; i < 8; i++) {
                     W.w[i] = Fo.w[i] & ~Fc.w[i];
@@ -422,35 +485,31 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
     }
 
     // Phase 2: every parent entry of the tile (Fig. 3 "compute").
-    const int mD = J.m[D];
-    const int total = nlines * mD;
+    // slots: 8 per line per position along D (memory order inside a block:
+    // for D = 3 the line r2 is slower and r3 faster), unused slots skipped
+    const int total = D == 3 ? 64 * ((mD + 7) >> 3) : 8 * mD;
     for (int it = threadIdx.x; it < total; it += blockDim.x) {
         int v, iD;
         if (D == 3) {
-            // memory order inside a block: line (r2) slower, r3 faster
-            const int B3 = it / (8 * nlines);
-            const int rem = it - B3 * 8 * nlines;
-            const int s3 = min(8, mD - 8 * B3);
-            v = rem / s3;
-            iD = 8 * B3 + rem % s3;
+            v = (it >> 3) & 7;
+            iD = 8 * (it >> 6) + (it & 7);
         } else {
-            v = it % nlines;
-            iD = it / nlines;
+            v = it & 7;
+            iD = it >> 3;
         }
+        if (v >= nlines || iD >= mD) continue;
         Idx4 idx = base;
         set4(idx, J.e, get4(base, J.e) + v);
         idx.v[D] = iD;
-        const QInfo qD = T.qinfo[J.qb[D] + iD];
+        const PosRec &pr = L.pos[iD];
 
         Set256 Wnt = s_zero(), Nnt = s_zero();
         if (J.emask == 0) Nnt = s_full();
         if (staged) {
-            unsigned empt = ~(unsigned)(qD.bm | qD.wm) & 0x1ffu;
             const uint32_t *line = L.rec + kRecWords * (v * cmD);
-            while (empt) {
-                const int cell = __builtin_ctz(empt);
-                empt &= empt - 1;
-                const uint16_t cc = T.canon[qD.code + c * c_pow3[cell]];
+            const int n = pr.nchild;
+            for (int e = 0; e < n; e++) {
+                const uint16_t cc = pr.child[e];
                 const uint32_t *r = line + kRecWords * (cc & 0xfff);
                 or_rotated(Wnt, r, cc >> 12);
                 or_rotated(Nnt, r + 8, cc >> 12);
@@ -466,9 +525,9 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
             if (D != 2 && (J.emask & 4)) direct_children<D, 2>(J, T, idx, q[2], Wnt, Nnt);
             if (D != 3 && (J.emask & 8)) direct_children<D, 3>(J, T, idx, q[3], Wnt, Nnt);
         }
-        const uint2 *lut = L.lut + 384 * v;
-        const Set256 Fc = five_lut(lut + 192 * (c - 1), T.sel[D * 512 + (c == 1 ? qD.bm : qD.wm)]);
-        const Set256 Fo = five_lut(lut + 192 * (2 - c), T.sel[D * 512 + (c == 1 ? qD.wm : qD.bm)]);
+        const uint2 *lut = L.lut + kLutStride * v;
+        const Set256 Fc = five_lut(lut + 192 * (c - 1), pr.sel_c);
+        const Set256 Fo = five_lut(lut + 192 * (2 - c), pr.sel_o);
         Set256 W, N;
         combine(Fc, Fo, Wnt, Nnt, W, N);
         swap_with3<D>(W);

@@ -60,7 +60,8 @@ PG_HD uint32_t swap_bytes16(uint32_t x) { return ((x >> 8) & 0x00ff00ffu) | ((x 
 
 // rmax(X)(g) = OR over the 8 single-quadrant turns r of X(g + r) (Section III).
 // Along each dimension the two neighbours g_j +- 1 of g_j are the two values
-// of the other parity, so each dimension costs a pair-swap plus an OR.
+// of the other parity, so each dimension costs a pair-swap plus an OR:
+// OR in the element two steps away, then exchange the two parities.
 PG_HD Set256 rmax(const Set256 &x)
 {
     Set256 r;
@@ -78,12 +79,12 @@ PG_HD Set256 rmax(const Set256 &x)
         const int g3 = w >> 1, p = w & 1;
         const uint32_t u = x.w[w];
         // dimension 0: bits inside nibbles
-        const uint32_t y0 = u | bfi(0x33333333u, u >> 2, u << 2);
-        const uint32_t n0 = bfi(0x55555555u, y0 >> 1, y0 << 1);
-        // dimension 1: nibbles inside halves
-        const uint32_t y1 = u | swap_bytes16(u);
-        const uint32_t n1 = bfi(0x0f0f0f0fu, y1 >> 4, y1 << 4);
-        r.w[w] = n0 | n1 | n2[g3] | n3[(g3 & 1) * 2 + p];
+        const uint32_t y0 = ((u >> 2) & 0x33333333u) | ((u << 2) & 0xccccccccu) | u;
+        const uint32_t n0 = ((y0 >> 1) & 0x55555555u) | ((y0 << 1) & 0xaaaaaaaau);
+        // dimension 1: nibbles inside halves (a byte swap inside each half)
+        const uint32_t y1 = swap_bytes16(u) | u;
+        const uint32_t n1 = ((y1 >> 4) & 0x0f0f0f0fu) | ((y1 << 4) & 0xf0f0f0f0u);
+        r.w[w] = (n0 | n1) | (n2[g3] | n3[(g3 & 1) * 2 + p]);
     }
     return r;
 }

@@ -146,11 +146,15 @@ static void build_line_structure(HostTables &t)
             const LineMasks &L = t.lm[j * 512 + m];
             const uint32_t f[3] = {L.a, L.b, L.c};
             for (int k = 0; k < 4; k++) {
-                uint32_t v = 0;
-                for (int ff = 0; ff < 3; ff++)
+                uint32_t off = 0;
+                for (int ff = 0; ff < 3; ff++) {
+                    uint32_t sigma = 0;
                     for (int sl = 0; sl < 6; sl++)
-                        if ((f[ff] >> (4 * sl + k)) & 1) v |= 1u << (6 * ff + sl);
-                t.sel[(j * 512 + m) * 4 + k] = v;
+                        if ((f[ff] >> (4 * sl + k)) & 1) sigma |= 1u << sl;
+                    // byte offset of entry sigma of chunk ff: 8 * (64 ff + sigma)
+                    off |= (8u * (64u * ff + sigma)) << (10 * ff);
+                }
+                t.sel[(j * 512 + m) * 4 + k] = off;
             }
         }
     t.chunk_ref.assign(4 * 18, 0xffff);

@@ -27,11 +27,13 @@ struct HostTables {
     std::vector<uint16_t> turn1;  // per code: code after one counter-clockwise turn
     std::vector<LineMasks> lm;    // [quadrant * 512 + stone mask]
 
-    // Line structure used by the sweep (see LineSelect in kernels.h):
-    // sel[j * 512 + m] holds, for k = 0..3, the 18-bit selector of the lines
-    // through quadrant j that its pattern m completes after k turns: bit s of
-    // chunk f (6 bits each, f = fields a, b, c of LineMasks) set iff nibble s
-    // of field f of lm[j*512+m] contains k.
+    // Line structure used by the sweep (five_lut in kernels.hip):
+    // sel[(j * 512 + m) * 4 + k] describes the lines through quadrant j that
+    // its stone mask m completes after k turns.  For each field f = a, b, c of
+    // LineMasks the 6-bit set sigma_f (bit s iff nibble s of field f of
+    // lm[j*512+m] contains k) is stored as the byte offset 8 * (64 f + sigma_f)
+    // of its entry in a line's chunk tables, in bits [10 f, 10 f + 10) (the
+    // third field takes 11 bits).
     std::vector<uint32_t> sel;    // [4 * 512 * 4]
     // chunk_ref[D * 18 + 6f + s]: the other quadrants of the line kept in
     // nibble s of field f of quadrant D's LineMasks, as up to two refs

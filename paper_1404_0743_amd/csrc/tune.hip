@@ -1,0 +1,109 @@
+// tune.hip -- the tile autotuner of the sweep: times the tile shapes a
+// section admits (lines per tile) and remembers the fastest per section
+// geometry, so later sweeps of the same geometry use it.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "internal.h"
+
+namespace pg {
+
+using TileKey = std::tuple<int, int, int, int, int, int, int>;
+static std::mutex g_tune_mutex;
+static std::map<TileKey, int> g_tile_cache;
+
+static TileKey tile_key(const SweepJob &J)
+{
+    return TileKey(J.m[0], J.m[1], J.m[2], J.m[3], J.d, J.emask, J.cm[J.d]);
+}
+
+int tuned_tile_lines(const SweepJob &J)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    auto it = g_tile_cache.find(tile_key(J));
+    return it == g_tile_cache.end() ? 0 : it->second;
+}
+
+void remember_tile_lines(const SweepJob &J, int G)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tile_cache[tile_key(J)] = G;
+}
+
+// Launch prep passes and the sweep of one job (prep buffers stream-ordered).
+int run_job(SweepJob &J, const DevTables &T, hipStream_t st)
+{
+    void *prep[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < 4 && e == hipSuccess; j++) {
+        if (j == J.d || !((J.emask >> j) & 1)) continue;
+        e = hipMallocAsync(&prep[j], prep_bytes(J, j), st);
+        if (e != hipSuccess) break;
+        J.prep[j] = J.prep_out[j] = (uint4 *)prep[j];
+        e = launch_prep(J, j, T, st);
+    }
+    if (e == hipSuccess) e = launch_sweep(J, T, st);
+    for (int j = 0; j < 4; j++)
+        if (prep[j]) (void)hipFreeAsync(prep[j], st);
+    if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    return 0;
+}
+
+}  // namespace pg
+
+using namespace pg;
+
+extern "C" int pentago_autotune_section(pentago_section s, const pentago_superinfo *const child[4],
+                                        pentago_superinfo *out, void *hip_stream, int *tile_lines,
+                                        float *best_ms)
+{
+    DevTables T;
+    int rc = device_tables(&T);
+    if (rc) return rc;
+    SweepJob J0;
+    rc = make_job(s, child, out, &J0, -1, 0);
+    if (rc) return rc;
+    const hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return fail(PENTAGO_EDEVICE, "hipEventCreate");
+    int bestG = 0;
+    float best = 1e30f;
+    const int cmd = (J0.emask >> J0.d) & 1 ? J0.cm[J0.d] : 0;
+    for (int G = 1; G <= 8 && rc == 0; G++) {
+        if (sweep_lds_bytes(G, J0.m[J0.d], cmd) > 65536) break;
+        SweepJob J;
+        rc = make_job(s, child, out, &J, -1, G);
+        if (rc) break;
+        rc = run_job(J, T, st);  // warm-up
+        float t = 1e30f;
+        for (int rep = 0; rep < 3 && rc == 0; rep++) {
+            (void)hipEventRecord(a, st);
+            rc = run_job(J, T, st);
+            (void)hipEventRecord(b, st);
+            if (hipEventSynchronize(b) != hipSuccess) rc = fail(PENTAGO_EDEVICE, "hipEventSynchronize");
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, a, b);
+            t = std::min(t, ms);
+        }
+        if (rc == 0 && t < best) {
+            best = t;
+            bestG = G;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return rc;
+    remember_tile_lines(J0, bestG);
+    // leave out holding the result of the chosen shape
+    SweepJob J;
+    rc = make_job(s, child, out, &J, -1, bestG);
+    if (rc == 0) rc = run_job(J, T, st);
+    if (tile_lines) *tile_lines = bestG;
+    if (best_ms) *best_ms = best;
+    return rc;
+}

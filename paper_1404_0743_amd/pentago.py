@@ -61,6 +61,7 @@ _SIGS = {
     "pentago_child_section": ([Section, ctypes.c_int, _P], ctypes.c_int),
     "pentago_solve_section": ([Section, _P, _P, _P], ctypes.c_int),
     "pentago_solve_sections": ([_P, ctypes.c_size_t, _P], ctypes.c_int),
+    "pentago_autotune_section": ([Section, _P, _P, _P, _P, _P], ctypes.c_int),
     "pentago_eval_batch": ([_P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
     "pentago_eval_batch_grouped": ([_P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
     "pentago_serve_create": ([_P, _P], ctypes.c_int),
@@ -193,6 +194,17 @@ def pentago_solve_section(counts, children, out, stream=None):
             _dev_ptr(c)
     _check(lib().pentago_solve_section(section(counts), ch, _dev_ptr(out), _stream(stream)),
            "pentago_solve_section")
+
+
+def pentago_autotune_section(counts, children, out, stream=None):
+    """Time the tile shapes of this section geometry, remember the fastest;
+    returns (tile lines, best ms).  out holds the sweep's result afterwards."""
+    ch = (ctypes.c_void_p * 4)(*[None if c is None else c.data_ptr() for c in children])
+    g = ctypes.c_int()
+    ms = ctypes.c_float()
+    _check(lib().pentago_autotune_section(section(counts), ch, _dev_ptr(out), _stream(stream),
+                                          ctypes.byref(g), ctypes.byref(ms)), "pentago_autotune_section")
+    return g.value, ms.value
 
 
 def pentago_solve_sections(jobs, stream=None):
