@@ -136,6 +136,25 @@ typedef struct {
  * write to any table another job of the same call reads.  n <= 65536. */
 int pentago_solve_sections(const pentago_section_job *jobs, size_t n, void *hip_stream);
 
+/* A sweep plan: the job table of one layer (as for pentago_solve_sections)
+ * uploaded once, with the prepared-child buffers it needs, so that the layer
+ * can be launched repeatedly, directly or from a captured hipGraph.  The
+ * tables the jobs name are borrowed until pentago_plan_destroy.
+ * pentago_plan_create synchronises the device while uploading. */
+typedef struct pentago_sweep_plan pentago_sweep_plan;
+int pentago_plan_create(const pentago_section_job *jobs, size_t n, pentago_sweep_plan **plan);
+/* Enqueue the layer on hip_stream: one batched prep launch (children along
+ * dimensions that are not staged) and one persistent sweep launch. */
+int pentago_plan_launch(pentago_sweep_plan *plan, void *hip_stream);
+/* The same work as one hipGraph: captured on the plan's own stream at the
+ * first call, replayed on hip_stream at every call.  Launches of one plan
+ * must not overlap. */
+int pentago_plan_launch_graph(pentago_sweep_plan *plan, void *hip_stream);
+/* Work tiles of the layer, persistent grid size and LDS bytes per workgroup. */
+int pentago_plan_info(const pentago_sweep_plan *plan, long long *tiles, int *grid, int *lds_bytes);
+/* Waits for the plan's work, then releases it. */
+int pentago_plan_destroy(pentago_sweep_plan *plan);
+
 /* ---------------------------------------------------------------- endgame */
 
 /* Exact superinfo of n arbitrary boards, each solved to the full board over

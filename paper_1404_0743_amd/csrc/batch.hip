@@ -1,0 +1,218 @@
+// batch.hip -- many sections of one slice in one persistent launch (the
+// whole layer's block lines as one work queue, Section IV-A's "each process
+// computes its block lines in any order" on one GPU), plus the sweep plan that
+// keeps the layer's job table resident and replays it from a hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+using namespace pg;
+
+struct pentago_sweep_plan {
+    int device = 0;
+    int njobs = 0, nunits = 0;
+    long long total_tiles = 0, total_chunks = 0;
+    int lds_bytes = 0, grid = 0;
+    char *dev = nullptr;  // one device block: jobs, tile starts, units, chunk starts, counter, prep
+    SweepJob *d_jobs = nullptr;
+    long long *d_tile_start = nullptr;
+    int *d_unit = nullptr;
+    long long *d_chunk_start = nullptr;
+    unsigned long long *d_counter = nullptr;
+    bool async_alloc = false;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    DevTables T;
+};
+
+namespace pg {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Build a plan: job table in decreasing order of work, prep units for the
+// dimensions that are not staged, and the device block holding all of it.
+// With `stream` the device block is allocated stream-ordered on it.
+static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t stream, bool async,
+                      pentago_sweep_plan **out)
+{
+    if (!jobs || n == 0) return fail(PENTAGO_EINVAL, "no jobs");
+    if (n > 65536) return fail(PENTAGO_ERANGE, "more than 65536 jobs");
+    const int stones = section_stones(jobs[0].section);
+    std::vector<SweepJob> J(n);
+    for (size_t i = 0; i < n; i++) {
+        if (section_stones(jobs[i].section) != stones)
+            return fail(PENTAGO_EINVAL, "jobs of one call must share the stone count");
+        int rc = make_job(jobs[i].section, jobs[i].child, jobs[i].out, &J[i], -1, 0);
+        if (rc) return rc;
+    }
+    // largest sections first: their tiles start early and small ones fill the tail
+    std::vector<size_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    auto work = [&](size_t i) { return (double)J[i].m[0] * J[i].m[1] * J[i].m[2] * J[i].m[3]; };
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return work(a) > work(b); });
+    std::vector<SweepJob> S(n);
+    for (size_t i = 0; i < n; i++) S[i] = J[order[i]];
+
+    std::vector<long long> tile_start(n);
+    long long tiles = 0;
+    int lds = 0;
+    for (size_t i = 0; i < n; i++) {
+        tile_start[i] = tiles;
+        tiles += S[i].ntiles;
+        lds = std::max(lds, S[i].lds_bytes);
+    }
+    std::vector<int> unit;
+    std::vector<long long> chunk_start;
+    std::vector<size_t> prep_off;
+    size_t prep_total = 0;
+    long long chunks = 0;
+    for (size_t i = 0; i < n; i++)
+        for (int j = 0; j < 4; j++) {
+            if (j == S[i].d || !((S[i].emask >> j) & 1)) continue;
+            unit.push_back((int)(i << 2) | j);
+            chunk_start.push_back(chunks);
+            const size_t bytes = prep_bytes(S[i], j);
+            chunks += (long long)((bytes / 64 + 255) / 256);
+            prep_off.push_back(prep_total);
+            prep_total += align256(bytes);
+        }
+
+    pentago_sweep_plan *P = new pentago_sweep_plan;
+    (void)hipGetDevice(&P->device);
+    int rc = device_tables(&P->T);
+    if (rc) { delete P; return rc; }
+    P->njobs = (int)n;
+    P->nunits = (int)unit.size();
+    P->total_tiles = tiles;
+    P->total_chunks = chunks;
+    P->lds_bytes = lds;
+    P->async_alloc = async;
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device);
+    P->grid = std::max(1, cus) * sweep_batch_blocks_per_cu(lds);
+
+    const size_t o_jobs = 0;
+    const size_t o_tiles = align256(o_jobs + n * sizeof(SweepJob));
+    const size_t o_unit = align256(o_tiles + n * sizeof(long long));
+    const size_t o_chunk = align256(o_unit + unit.size() * sizeof(int) + 4);
+    const size_t o_counter = align256(o_chunk + chunk_start.size() * sizeof(long long) + 8);
+    const size_t o_prep = align256(o_counter + 8);
+    const size_t total = o_prep + prep_total;
+    hipError_t e = async ? hipMallocAsync((void **)&P->dev, total, stream) : hipMalloc((void **)&P->dev, total);
+    if (e != hipSuccess) { delete P; return hip_fail(e, "plan allocation"); }
+    P->d_jobs = (SweepJob *)(P->dev + o_jobs);
+    P->d_tile_start = (long long *)(P->dev + o_tiles);
+    P->d_unit = (int *)(P->dev + o_unit);
+    P->d_chunk_start = (long long *)(P->dev + o_chunk);
+    P->d_counter = (unsigned long long *)(P->dev + o_counter);
+    size_t u = 0;
+    for (size_t i = 0; i < n; i++)
+        for (int j = 0; j < 4; j++) {
+            if (j == S[i].d || !((S[i].emask >> j) & 1)) continue;
+            uint4 *p = (uint4 *)(P->dev + o_prep + prep_off[u++]);
+            S[i].prep[j] = p;
+            S[i].prep_out[j] = p;
+        }
+    // one host image of the table block, copied in one transfer
+    std::vector<char> img(o_counter, 0);
+    memcpy(img.data() + o_jobs, S.data(), n * sizeof(SweepJob));
+    memcpy(img.data() + o_tiles, tile_start.data(), n * sizeof(long long));
+    if (!unit.empty()) {
+        memcpy(img.data() + o_unit, unit.data(), unit.size() * sizeof(int));
+        memcpy(img.data() + o_chunk, chunk_start.data(), chunk_start.size() * sizeof(long long));
+    }
+    e = async ? hipMemcpyAsync(P->dev, img.data(), img.size(), hipMemcpyHostToDevice, stream)
+              : hipMemcpy(P->dev, img.data(), img.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && async) e = hipStreamSynchronize(stream);  // img is freed on return
+    if (e != hipSuccess) { (void)hipFree(P->dev); delete P; return hip_fail(e, "plan upload"); }
+    *out = P;
+    return 0;
+}
+
+static int plan_enqueue(pentago_sweep_plan *P, hipStream_t st)
+{
+    hipError_t e = launch_prep_batch(P->d_jobs, P->d_unit, P->d_chunk_start, P->nunits,
+                                     P->total_chunks, P->T, st);
+    if (e == hipSuccess)
+        e = launch_sweep_batch(P->d_jobs, P->d_tile_start, P->njobs, P->total_tiles, P->lds_bytes,
+                               P->d_counter, P->grid, P->T, st);
+    if (e != hipSuccess) return hip_fail(e, "batched sweep launch");
+    return 0;
+}
+
+}  // namespace pg
+
+extern "C" {
+
+int pentago_plan_create(const pentago_section_job *jobs, size_t n, pentago_sweep_plan **plan)
+{
+    if (!plan) return fail(PENTAGO_EINVAL, "plan is NULL");
+    return plan_build(jobs, n, nullptr, false, plan);
+}
+
+int pentago_plan_launch(pentago_sweep_plan *plan, void *hip_stream)
+{
+    if (!plan) return fail(PENTAGO_EINVAL, "plan is NULL");
+    return plan_enqueue(plan, (hipStream_t)hip_stream);
+}
+
+int pentago_plan_launch_graph(pentago_sweep_plan *plan, void *hip_stream)
+{
+    if (!plan) return fail(PENTAGO_EINVAL, "plan is NULL");
+    hipError_t e;
+    if (!plan->exec) {
+        e = hipStreamCreateWithFlags(&plan->capture, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+        e = hipStreamBeginCapture(plan->capture, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        int rc = plan_enqueue(plan, plan->capture);
+        e = hipStreamEndCapture(plan->capture, &plan->graph);
+        if (rc) return rc;
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    }
+    e = hipGraphLaunch(plan->exec, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return 0;
+}
+
+int pentago_plan_info(const pentago_sweep_plan *plan, long long *tiles, int *grid, int *lds_bytes)
+{
+    if (!plan) return fail(PENTAGO_EINVAL, "plan is NULL");
+    if (tiles) *tiles = plan->total_tiles;
+    if (grid) *grid = plan->grid;
+    if (lds_bytes) *lds_bytes = plan->lds_bytes;
+    return 0;
+}
+
+int pentago_plan_destroy(pentago_sweep_plan *plan)
+{
+    if (!plan) return 0;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->capture) (void)hipStreamDestroy(plan->capture);
+    if (plan->dev) (void)hipFree(plan->dev);  // waits for work that uses it
+    delete plan;
+    return 0;
+}
+
+int pentago_solve_sections(const pentago_section_job *jobs, size_t n, void *hip_stream)
+{
+    const hipStream_t st = (hipStream_t)hip_stream;
+    pentago_sweep_plan *P = nullptr;
+    int rc = plan_build(jobs, n, st, true, &P);
+    if (rc) return rc;
+    rc = plan_enqueue(P, st);
+    (void)hipFreeAsync(P->dev, st);
+    delete P;
+    return rc;
+}
+
+}  // extern "C"

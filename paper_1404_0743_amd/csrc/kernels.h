@@ -53,6 +53,10 @@ struct SweepJob {
 hipError_t launch_sweep(const SweepJob &job, const DevTables &T, hipStream_t s);
 // Prepare the A/B child terms of dimension j (j in emask, j != d).
 hipError_t launch_prep(const SweepJob &job, int j, const DevTables &T, hipStream_t s);
+hipError_t launch_prep_batch(const SweepJob *dev_jobs, const int *dev_unit,
+                             const long long *dev_chunk_start, int nunits, long long total_chunks,
+                             const DevTables &T, hipStream_t s);
+int sweep_batch_blocks_per_cu(int lds_bytes);
 hipError_t launch_sweep_batch(const SweepJob *dev_jobs, const long long *dev_tile_start, int njobs,
                               long long total_tiles, int lds_bytes, unsigned long long *dev_counter,
                               int grid, const DevTables &T, hipStream_t s);

@@ -306,28 +306,67 @@ __device__ __forceinline__ void direct_children(const SweepJob &J, const DevTabl
 // that a sweep does not stage in LDS), written in the internal layout of the
 // parent's sweep (dimension J.d exchanged with 3).
 template <int JD>
-__global__ void __launch_bounds__(256) prep_kernel(SweepJob J, DevTables T)
+__device__ __forceinline__ void prep_entry(const SweepJob &J, const DevTables &T, long long i)
 {
     int cshape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
     cshape[JD] = J.cm[JD];
-    const long long n = (long long)cshape[0] * cshape[1] * cshape[2] * cshape[3];
+    Idx4 idx;
+    long long r = i;
+    idx.v[3] = (int)(r % cshape[3]); r /= cshape[3];
+    idx.v[2] = (int)(r % cshape[2]); r /= cshape[2];
+    idx.v[1] = (int)(r % cshape[1]); r /= cshape[1];
+    idx.v[0] = (int)r;
+    Set256 A, B;
+    child_entry_terms<JD>(J, T, idx, A, B);
+    swap_with3_rt(A, J.d);
+    swap_with3_rt(B, J.d);
+    uint4 *p = J.prep_out[JD] + 4 * block_offset(cshape, idx.v);
+    p[0] = make_uint4(A.w[0], A.w[1], A.w[2], A.w[3]);
+    p[1] = make_uint4(A.w[4], A.w[5], A.w[6], A.w[7]);
+    p[2] = make_uint4(B.w[0], B.w[1], B.w[2], B.w[3]);
+    p[3] = make_uint4(B.w[4], B.w[5], B.w[6], B.w[7]);
+}
+
+__device__ __forceinline__ long long prep_count(const SweepJob &J, int jd)
+{
+    long long n = jd == 0 ? J.cm[0] : jd == 1 ? J.cm[1] : jd == 2 ? J.cm[2] : J.cm[3];
+    for (int i = 0; i < 4; i++)
+        if (i != jd) n *= (i == 0 ? J.m[0] : i == 1 ? J.m[1] : i == 2 ? J.m[2] : J.m[3]);
+    return n;
+}
+
+template <int JD>
+__global__ void __launch_bounds__(256) prep_kernel(SweepJob J, DevTables T)
+{
+    const long long n = prep_count(J, JD);
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        Idx4 idx;
-        long long r = i;
-        idx.v[3] = (int)(r % cshape[3]); r /= cshape[3];
-        idx.v[2] = (int)(r % cshape[2]); r /= cshape[2];
-        idx.v[1] = (int)(r % cshape[1]); r /= cshape[1];
-        idx.v[0] = (int)r;
-        Set256 A, B;
-        child_entry_terms<JD>(J, T, idx, A, B);
-        swap_with3_rt(A, J.d);
-        swap_with3_rt(B, J.d);
-        uint4 *p = J.prep_out[JD] + 4 * block_offset(cshape, idx.v);
-        p[0] = make_uint4(A.w[0], A.w[1], A.w[2], A.w[3]);
-        p[1] = make_uint4(A.w[4], A.w[5], A.w[6], A.w[7]);
-        p[2] = make_uint4(B.w[0], B.w[1], B.w[2], B.w[3]);
-        p[3] = make_uint4(B.w[4], B.w[5], B.w[6], B.w[7]);
+         i += (long long)gridDim.x * blockDim.x)
+        prep_entry<JD>(J, T, i);
+}
+
+// Prep passes of many jobs in one launch: unit u = (job, dimension), its
+// 256-entry chunks numbered from chunk_start[u].
+__global__ void __launch_bounds__(256)
+    prep_batch_kernel(const SweepJob *jobs, const int *unit, const long long *chunk_start, int nunits,
+                      long long total, DevTables T)
+{
+    for (long long ch = blockIdx.x; ch < total; ch += gridDim.x) {
+        int lo = 0, hi = nunits - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (chunk_start[mid] <= ch) lo = mid;
+            else hi = mid - 1;
+        }
+        const int job = unit[lo] >> 2, jd = unit[lo] & 3;
+        const SweepJob &J = jobs[job];
+        const long long i = (ch - chunk_start[lo]) * 256 + threadIdx.x;
+        if (i >= prep_count(J, jd)) continue;
+        switch (jd) {
+        case 0: prep_entry<0>(J, T, i); break;
+        case 1: prep_entry<1>(J, T, i); break;
+        case 2: prep_entry<2>(J, T, i); break;
+        default: prep_entry<3>(J, T, i); break;
+        }
     }
 }
 
@@ -608,6 +647,25 @@ hipError_t launch_sweep(const SweepJob &job, const DevTables &T, hipStream_t s)
     default: hipLaunchKernelGGL(sweep_kernel<3>, grid, block, job.lds_bytes, s, job, T); break;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_prep_batch(const SweepJob *dev_jobs, const int *dev_unit,
+                             const long long *dev_chunk_start, int nunits, long long total_chunks,
+                             const DevTables &T, hipStream_t s)
+{
+    if (nunits == 0 || total_chunks == 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<long long>(total_chunks, 1 << 16);
+    hipLaunchKernelGGL(prep_batch_kernel, dim3(grid), dim3(256), 0, s, dev_jobs, dev_unit,
+                       dev_chunk_start, nunits, total_chunks, T);
+    return hipGetLastError();
+}
+
+int sweep_batch_blocks_per_cu(int lds_bytes)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_batch_kernel, 256, lds_bytes) != hipSuccess)
+        return 1;
+    return std::max(1, n);
 }
 
 hipError_t launch_sweep_batch(const SweepJob *dev_jobs, const long long *dev_tile_start, int njobs,

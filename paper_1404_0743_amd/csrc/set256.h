@@ -159,8 +159,9 @@ PG_HD void swap_index_bits(Set256 &x)
 template <int D>
 PG_HD void swap_with3(Set256 &x)
 {
-    if (D == 3) return;
-    if (D == 2) {
+    if constexpr (D == 3) {
+        return;
+    } else if constexpr (D == 2) {
         // index bit 4 (half) <-> bit 6 (word bit 1); bit 5 (word bit 0) <-> bit 7 (word bit 2)
         swap_index_bits<4, 1>(x);
         uint32_t t = x.w[1]; x.w[1] = x.w[4]; x.w[4] = t;

@@ -62,6 +62,11 @@ _SIGS = {
     "pentago_solve_section": ([Section, _P, _P, _P], ctypes.c_int),
     "pentago_solve_sections": ([_P, ctypes.c_size_t, _P], ctypes.c_int),
     "pentago_autotune_section": ([Section, _P, _P, _P, _P, _P], ctypes.c_int),
+    "pentago_plan_create": ([_P, ctypes.c_size_t, _P], ctypes.c_int),
+    "pentago_plan_launch": ([_P, _P], ctypes.c_int),
+    "pentago_plan_launch_graph": ([_P, _P], ctypes.c_int),
+    "pentago_plan_info": ([_P, _P, _P, _P], ctypes.c_int),
+    "pentago_plan_destroy": ([_P], ctypes.c_int),
     "pentago_eval_batch": ([_P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
     "pentago_eval_batch_grouped": ([_P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
     "pentago_serve_create": ([_P, _P], ctypes.c_int),
@@ -207,15 +212,52 @@ def pentago_autotune_section(counts, children, out, stream=None):
     return g.value, ms.value
 
 
-def pentago_solve_sections(jobs, stream=None):
-    """jobs: list of (counts, children (4 tensors or None), out tensor)."""
+def _job_array(jobs):
     arr = (SectionJob * len(jobs))()
     for k, (counts, children, out) in enumerate(jobs):
         arr[k].section = section(counts)
         for j in range(4):
             arr[k].child[j] = None if children[j] is None else children[j].data_ptr()
         arr[k].out = out.data_ptr()
+    return arr
+
+
+def pentago_solve_sections(jobs, stream=None):
+    """jobs: list of (counts, children (4 tensors or None), out tensor)."""
+    arr = _job_array(jobs)
     _check(lib().pentago_solve_sections(arr, len(jobs), _stream(stream)), "pentago_solve_sections")
+
+
+class SweepPlan:
+    """pentago_plan_*: one layer's job table kept on the device."""
+
+    def __init__(self, jobs):
+        self._keep = jobs
+        h = ctypes.c_void_p()
+        _check(lib().pentago_plan_create(_job_array(jobs), len(jobs), ctypes.byref(h)),
+               "pentago_plan_create")
+        self.h = h
+
+    def launch(self, stream=None, graph=False):
+        f = lib().pentago_plan_launch_graph if graph else lib().pentago_plan_launch
+        _check(f(self.h, _stream(stream)), "pentago_plan_launch" + ("_graph" if graph else ""))
+
+    def info(self):
+        t, g, l = ctypes.c_longlong(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().pentago_plan_info(self.h, ctypes.byref(t), ctypes.byref(g), ctypes.byref(l)),
+               "pentago_plan_info")
+        return {"tiles": t.value, "grid": g.value, "lds_bytes": l.value}
+
+    def close(self):
+        if self.h:
+            lib().pentago_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------- endgame
