@@ -10,7 +10,7 @@ Prints one JSON line: throughput in positions/s, the roofline of the sweep
 kernel (algorithmic bytes over HIP-event time on the launch stream) and the
 CPU oracle timed on a bounded sample of the same section.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extra]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
 """
 import argparse
 import json
@@ -63,7 +63,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extra", action="store_true", help="also time the other workloads")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (endgame batches, uneven layers)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -71,6 +72,14 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the sweep would shard)", file=sys.stderr)
         sys.exit(2)
+
+    boards_2p20 = None
+    if not args.no_extra:
+        # generated before the GPU is touched (the generator forks workers)
+        from paper_1404_0743_amd import inputs as I
+        t0 = time.perf_counter()
+        boards_2p20 = I.random_play_boards(1 << 20, 28, 33)
+        log("generated 2^20 endgame roots in %.1f s" % (time.perf_counter() - t0))
 
     import torch
     from paper_1404_0743_amd import pentago as P
@@ -149,9 +158,11 @@ def main():
         "kernel_ms": {"sweep_avg": avg_ms, "sweep_min": float(np.min(kernel_ms)),
                       "terminal_child_section": terminal_ms},
     }
-    if args.extra:
+    if not args.no_extra:
         import bench_extra
-        res["extra"] = bench_extra.run_all(P, torch, stream)
+        del out, child, children
+        torch.cuda.empty_cache()
+        res["extra"] = bench_extra.run_all(P, torch, stream, boards_2p20)
     if not args.no_cpu:
         log("timing the CPU oracle on a sample ...")
         res["cpu_baseline"] = cpu_baseline(entries, positions)

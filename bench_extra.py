@@ -1,0 +1,136 @@
+"""The workloads beside the headline sweep, timed on the GPU for bench.py.
+
+  endgame_4096   4096 boards with 17 black and 16 white stones (3 empty
+                 cells), solved to the full board: pentago_eval_batch.
+  endgame_2p20   2^20 boards with 28..33 stones from random legal play:
+                 one persistent launch (pentago_eval_batch) against one launch
+                 per empties group (pentago_eval_batch_grouped).
+  layers         64 sections per slice for slices 35, 34, 33 (sizes 1e4..2e8
+                 positions, stratified by size), child chains solved first
+                 (untimed): one persistent launch per layer replayed from a
+                 hipGraph against 64 per-section launches.
+Inputs are resident on the GPU when timing starts; times are HIP events on
+the launch stream.
+"""
+import math
+import sys
+import time
+
+import numpy as np
+
+from paper_1404_0743_amd import inputs as I
+
+# DAG nodes per root by number of empty cells e: sum over t of C(e,t) C(t, t//2)
+NODES = [sum(math.comb(e, t) * math.comb(t, t // 2) for t in range(e + 1)) for e in range(11)]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _time(torch, stream, fn, reps):
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts)), float(np.min(ts))
+
+
+def endgame(P, torch, stream, boards, grouped_too):
+    codes = torch.from_numpy(P.boards_to_codes(boards).view(np.int16).copy()).cuda()
+    out = torch.empty((len(boards), 8), dtype=torch.int64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    empt = (boards == 0).sum(axis=1)
+    nodes = int(sum(NODES[e] for e in empt))
+    res = {"roots": len(boards), "dag_nodes": nodes}
+    med, mn = _time(torch, stream, lambda: P.pentago_eval_batch(codes, out, status, stream), 5)
+    res.update(persistent_ms=med, persistent_roots_per_s=len(boards) / (med * 1e-3),
+               persistent_node_evals_per_s=nodes * 256 / (med * 1e-3))
+    if grouped_too:
+        ref = out.clone()
+        med2, _ = _time(torch, stream, lambda: P.pentago_eval_batch(codes, out, status, stream, grouped=True), 5)
+        res.update(grouped_ms=med2, grouped_roots_per_s=len(boards) / (med2 * 1e-3),
+                   persistent_over_grouped=med2 / med, same_bytes=bool(torch.equal(ref, out)))
+    res["invalid_boards"] = int(status.item())
+    return res
+
+
+def layers(P, torch, stream):
+    out = {}
+    cache = {}
+
+    def solve_chain(counts):
+        if counts in cache:
+            return cache[counts]
+        ch = [None] * 4
+        if sum(b + w for b, w in counts) < 35:
+            for j in range(4):
+                if sum(counts[j]) < 9:
+                    ch[j] = solve_chain(P.pentago_child_section(counts, j))
+        _, entries, _ = P.pentago_section_shape(counts)
+        t = torch.empty((entries, 8), dtype=torch.int64, device="cuda")
+        P.pentago_solve_section(counts, ch, t, stream)
+        cache[counts] = t
+        return t
+
+    for stones in (35, 34, 33):
+        secs = I.pick_layer_sections(stones)
+        jobs = []
+        positions = 0
+        for s in secs:
+            ch = [None] * 4
+            if stones < 35:
+                for j in range(4):
+                    if sum(s[j]) < 9:
+                        ch[j] = solve_chain(P.pentago_child_section(s, j))
+            _, entries, pos = P.pentago_section_shape(s)
+            positions += pos
+            jobs.append((s, ch, torch.empty((entries, 8), dtype=torch.int64, device="cuda")))
+        torch.cuda.synchronize()
+
+        def plain():
+            for s, ch, o in jobs:
+                P.pentago_solve_section(s, ch, o, stream)
+
+        med_plain, _ = _time(torch, stream, plain, 5)
+        ref = [o.clone() for _, _, o in jobs]
+        plan = P.SweepPlan(jobs)
+        med_graph, _ = _time(torch, stream, lambda: plan.launch(stream, graph=True), 5)
+        same = all(torch.equal(r, o) for r, (_, _, o) in zip(ref, jobs))
+        info = plan.info()
+        plan.close()
+        sizes = [I.section_positions(s) for s in secs]
+        out["slice%d" % stones] = {
+            "sections": len(secs), "positions": positions,
+            "min_positions": min(sizes), "max_positions": max(sizes),
+            "plain_ms": med_plain, "plain_positions_per_s": positions / (med_plain * 1e-3),
+            "batched_graph_ms": med_graph, "batched_positions_per_s": positions / (med_graph * 1e-3),
+            "batched_over_plain": med_plain / med_graph, "same_bytes": same,
+            "tiles": info["tiles"], "grid": info["grid"]}
+        log("layer %d: plain %.3f ms, batched %.3f ms" % (stones, med_plain, med_graph))
+    resident = sum(t.numel() * 8 for t in cache.values())
+    out["resident_child_bytes"] = resident
+    return out
+
+
+def run_all(P, torch, stream, boards_2p20=None):
+    res = {}
+    for name, fn in (("endgame_4096", lambda: endgame(P, torch, stream, I.random_placement_boards(4096, 17, 16), False)),
+                     ("endgame_2p20", lambda: endgame(P, torch, stream, boards_2p20, True)),
+                     ("layers", lambda: layers(P, torch, stream))):
+        if name == "endgame_2p20" and boards_2p20 is None:
+            continue
+        t0 = time.perf_counter()
+        try:
+            res[name] = fn()
+        except Exception as e:  # report, keep the headline line alive
+            res[name] = {"error": repr(e)}
+        log("%s done in %.1f s" % (name, time.perf_counter() - t0))
+    return res

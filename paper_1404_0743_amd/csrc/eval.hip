@@ -58,7 +58,7 @@ static int eval_alloc(size_t n, int grid, hipStream_t st, EvalAlloc *A)
 {
     const size_t ints = 64;
     const size_t glayer = (size_t)grid * 2 * kDagGlobalLayer * 64;
-    const size_t bytes = glayer + ints * 4 + 8 + n * 4 + n + 256;
+    const size_t bytes = glayer + ints * 4 + 16 + n * 4 + n + 256;
     hipError_t e = hipMallocAsync(&A->base, bytes, st);
     if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(eval scratch)");
     char *p = (char *)A->base;
@@ -69,7 +69,7 @@ static int eval_alloc(size_t n, int grid, hipStream_t st, EvalAlloc *A)
     A->S.cursor = A->S.count + 32;
     p += ints * 4;
     A->S.counter = (unsigned long long *)p;
-    p += 8;
+    p += 16;
     A->S.order = (int *)p;
     p += n * 4;
     A->S.empties = (uint8_t *)p;

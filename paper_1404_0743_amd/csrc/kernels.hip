@@ -732,13 +732,22 @@ __device__ __forceinline__ RootInfo decode_root(uint64_t packed)
     return r;
 }
 
-// Solve one root with a group of threads (the whole workgroup).  `buf0` and
-// `buf1` hold two layers of A/B records (64 B per node).
-__device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, uint4 *buf1,
-                           uint4 *out)
+__device__ __forceinline__ void wave_sync()
 {
-    __shared__ int s_slot_q[10], s_slot_l[10];
-    if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Solve one root with a group of GROUP threads: the whole workgroup (256) or
+// one wave (64).  `buf0` and `buf1` hold two layers of A/B records (64 B per
+// node); slot_q/slot_l (10 ints each, LDS) the root's empty cells.
+template <int GROUP>
+__device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, uint4 *buf1,
+                           uint4 *out, int *s_slot_q, int *s_slot_l)
+{
+    const int lane = GROUP == 256 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+    if (lane == 0) {
         int n = 0;
         for (int j = 0; j < 4; j++) {
             const unsigned empt = ~(R.bm[j] | R.wm[j]) & 0x1ffu;
@@ -750,7 +759,8 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
                 }
         }
     }
-    __syncthreads();
+    if (GROUP == 256) __syncthreads();
+    else wave_sync();
     const int e = R.e;
     const uint32_t *nodes = T.dag_node + T.dag_node_off[e];
     const uint16_t *rank = T.dag_rank + T.dag_rank_off[e];
@@ -760,7 +770,7 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
         const int n0 = layer[t], n1 = layer[t + 1];
         const int x = (t & 1) ? 3 - R.mover : R.mover;   // side to move at layer t
         const int xdigit = (t & 1) ? 2 : 1;              // slot digit of x's stones
-        for (int i = n0 + (int)threadIdx.x; i < n1; i += blockDim.x) {
+        for (int i = n0 + lane; i < n1; i += GROUP) {
             const uint32_t nd = nodes[i];
             const unsigned cmask = nd & 0xffffu, omask = nd >> 16;
             unsigned bm[4] = {R.bm[0], R.bm[1], R.bm[2], R.bm[3]};
@@ -819,7 +829,8 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
                 p[3] = make_uint4(B.w[4], B.w[5], B.w[6], B.w[7]);
             }
         }
-        __syncthreads();
+        if (GROUP == 256) __syncthreads();
+        else wave_sync();
         uint4 *tmp = cur;
         cur = prev;
         prev = tmp;
@@ -873,33 +884,52 @@ __global__ void zero_ints_kernel(int *p, int n)
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
-// Persistent solve over all valid roots, most empty cells first: workgroups
-// take roots from a device counter.  Roots with 9 or 10 empty cells keep
-// their two layers in the workgroup's slot of a global buffer (they exceed
-// LDS), the rest in LDS.
+// Persistent solve over all valid roots, most empty cells first, from two
+// device work queues: roots with more than kWaveMaxEmpties empty cells are
+// solved by a whole workgroup each (those with 9 or 10 keep their layers in
+// the workgroup's slot of a global buffer, the rest in LDS); the rest by one
+// wave each, four at a time per workgroup, synchronised per wave only.
+constexpr int kWaveMaxEmpties = 6;
+constexpr int kWaveLdsBytes = 2 * 90 * 64;  // two layers of the widest 6-empty layer
+
 __global__ void __launch_bounds__(256)
     eval_persistent_kernel(const uint64_t *boards, const int *order, const int *start,
                            unsigned long long *counter, uint4 *out, uint4 *gl, DevTables T)
 {
     extern __shared__ uint4 lds[];
     __shared__ long long s_item;
+    __shared__ int s_slots[4][2][10];
     const int nvalid = start[11];
-    const int big = start[8];  // roots with 9..10 empty cells occupy [0, big)
+    const int big = start[8];                    // roots with 9..10 empty cells: [0, big)
+    const int nwg = start[kWaveMaxEmpties];      // roots with > kWaveMaxEmpties: [0, nwg)
     uint4 *mine = gl + (size_t)blockIdx.x * 2 * 4 * kDagGlobalLayer;
     for (;;) {
-        if (threadIdx.x == 0) s_item = (long long)atomicAdd(counter, 1ull);
+        if (threadIdx.x == 0) s_item = (long long)atomicAdd(&counter[0], 1ull);
         __syncthreads();
         const long long item = s_item;
         __syncthreads();
+        if (item >= nwg) break;
+        const int root = order[item];
+        const RootInfo R = decode_root(boards[root]);
+        if (item < big)
+            solve_root<256>(R, T, mine, mine + 4 * kDagGlobalLayer, out + 4 * (size_t)root,
+                            s_slots[0][0], s_slots[0][1]);
+        else
+            solve_root<256>(R, T, lds, lds + 4 * T.dag_max[R.e], out + 4 * (size_t)root,
+                            s_slots[0][0], s_slots[0][1]);
+        __syncthreads();
+    }
+    const int w = threadIdx.x >> 6;
+    uint4 *wb = lds + (size_t)w * (kWaveLdsBytes / 16);
+    for (;;) {
+        unsigned long long got = 0;
+        if ((threadIdx.x & 63) == 0) got = atomicAdd(&counter[1], 1ull);
+        const long long item = nwg + (long long)__shfl(got, 0, 64);
         if (item >= nvalid) break;
         const int root = order[item];
         const RootInfo R = decode_root(boards[root]);
-        if (item < big) {
-            solve_root(R, T, mine, mine + 4 * kDagGlobalLayer, out + 4 * (size_t)root);
-        } else {
-            solve_root(R, T, lds, lds + 4 * T.dag_max[R.e], out + 4 * (size_t)root);
-        }
-        __syncthreads();
+        solve_root<64>(R, T, wb, wb + 4 * 90, out + 4 * (size_t)root, s_slots[w][0], s_slots[w][1]);
+        wave_sync();
     }
 }
 
@@ -910,14 +940,17 @@ __global__ void __launch_bounds__(256)
                       uint4 *gl, int use_global, DevTables T)
 {
     extern __shared__ uint4 lds[];
+    __shared__ int s_slots[2][10];
     uint4 *mine = gl + (size_t)blockIdx.x * 2 * 4 * kDagGlobalLayer;
     for (int item = blockIdx.x; item < count; item += gridDim.x) {
         const int root = order[first + item];
         const RootInfo R = decode_root(boards[root]);
         if (use_global)
-            solve_root(R, T, mine, mine + 4 * kDagGlobalLayer, out + 4 * (size_t)root);
+            solve_root<256>(R, T, mine, mine + 4 * kDagGlobalLayer, out + 4 * (size_t)root,
+                            s_slots[0], s_slots[1]);
         else
-            solve_root(R, T, lds, lds + 4 * T.dag_max[R.e], out + 4 * (size_t)root);
+            solve_root<256>(R, T, lds, lds + 4 * T.dag_max[R.e], out + 4 * (size_t)root,
+                            s_slots[0], s_slots[1]);
         __syncthreads();
     }
 }
@@ -955,7 +988,7 @@ hipError_t launch_eval_persistent(const uint64_t *boards, size_t n, uint4 *out,
     (void)n;
     hipError_t e = allow_lds((const void *)eval_persistent_kernel, dag_lds_bytes(8));
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, S.counter, 1);
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, S.counter, 2);
     hipLaunchKernelGGL(eval_persistent_kernel, dim3(grid), dim3(256), dag_lds_bytes(8), s, boards,
                        S.order, S.start, S.counter, out, S.global_layers, T);
     return hipGetLastError();

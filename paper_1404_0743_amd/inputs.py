@@ -87,37 +87,108 @@ def random_placement_boards(n, nblack, nwhite, seed=SEED_ENDGAME):
     return np.concatenate(out)[:n]
 
 
-def random_play_boards(n, stones_lo, stones_hi, seed=SEED_BATCH):
+def _turn_shifts():
+    """For each quadrant q and direction d (0 counter-clockwise, 1 clockwise):
+    the 9 (source bit, destination bit) pairs of the turn on a 36-bit board."""
+    out = np.zeros((4, 2, 9, 2), np.int64)
+    for q in range(4):
+        for d in range(2):
+            perm = _TURN[q, d]  # new[i] = old[perm[i]]
+            r0, c0 = 3 * (q // 2), 3 * (q % 2)
+            k = 0
+            for r in range(3):
+                for c in range(3):
+                    dst = 6 * (r0 + r) + c0 + c
+                    out[q, d, k] = (perm[dst], dst)
+                    k += 1
+    return out
+
+
+_SHIFTS = _turn_shifts()
+_QMASK = np.array([sum(1 << int(t) for t in _SHIFTS[q, 0, :, 1]) for q in range(4)], np.int64)
+_FULL = np.int64((1 << 36) - 1)
+
+
+def _five_bits(bb):
+    return ((bb[:, None] & _LINES[None, :]) == _LINES[None, :]).any(axis=1)
+
+
+def _turn_bits(bb, q, d):
+    out = bb.copy()
+    for qq in range(4):
+        for dd in range(2):
+            sel = (q == qq) & (d == dd)
+            if not sel.any():
+                continue
+            x = bb[sel]
+            y = x & ~_QMASK[qq]
+            for src, dst in _SHIFTS[qq, dd]:
+                y |= ((x >> src) & 1) << dst
+            out[sel] = y
+    return out
+
+
+_CHUNK = 1 << 15
+
+
+def random_play_boards(n, stones_lo, stones_hi, seed=SEED_BATCH, workers=None):
     """n boards from random legal play: the stone count is uniform in
     [stones_lo, stones_hi]; each ply puts the mover's stone (black first) on a
     uniform empty cell, then turns a uniform quadrant in a uniform direction.
-    A game that shows five in a row after any placement or turn is restarted."""
-    rng = np.random.default_rng(seed)
+    A game that shows five in a row after any placement or turn is restarted.
+    Boards come in fixed chunks of 2^15, chunk k drawn from the stream
+    (seed, k), so the result does not depend on how many worker processes
+    generate them (default: up to 16 for more than one chunk)."""
+    nchunks = (n + _CHUNK - 1) // _CHUNK
+    if nchunks <= 1:
+        return _play_chunk((n, stones_lo, stones_hi, seed, 0))
+    import multiprocessing as mp
+    args = [(min(_CHUNK, n - k * _CHUNK), stones_lo, stones_hi, seed, k) for k in range(nchunks)]
+    procs = workers or min(16, mp.cpu_count() or 1, nchunks)
+    if procs <= 1:
+        parts = [_play_chunk(a) for a in args]
+    else:
+        with mp.get_context("fork").Pool(procs) as pool:
+            parts = pool.map(_play_chunk, args)
+    return np.concatenate(parts)
+
+
+def _play_chunk(args):
+    n, stones_lo, stones_hi, seed, chunk = args
+    rng = np.random.default_rng([seed, chunk])
     target = rng.integers(stones_lo, stones_hi + 1, size=n)
     out = np.zeros((n, 36), np.uint8)
+    cells = np.arange(36, dtype=np.int64)
     for stones in range(stones_lo, stones_hi + 1):
         want = np.nonzero(target == stones)[0]
         got = []
         need = len(want)
         while need > 0:
             m = int(need * 1.3) + 64
-            b = np.zeros((m, 36), np.uint8)
+            bb = np.zeros((2, m), np.int64)  # black, white bit boards
             alive = np.ones(m, bool)
-            rows = np.arange(m)
             for ply in range(stones):
-                color = 1 if ply % 2 == 0 else 2
-                keys = rng.random((m, 36))
-                keys[b != 0] = -1.0
-                cell = keys.argmax(axis=1)
-                b[rows, cell] = color
-                alive &= ~has_five(b, color)
+                col = ply % 2
+                empty = _FULL & ~(bb[0] | bb[1])
+                cell = rng.integers(0, 36, size=m)
+                pending = ((empty >> cell) & 1) == 0
+                while pending.any():
+                    idx = np.nonzero(pending)[0]
+                    cell[idx] = rng.integers(0, 36, size=len(idx))
+                    pending[idx] = ((empty[idx] >> cell[idx]) & 1) == 0
+                bb[col] |= np.int64(1) << cell
+                alive &= ~_five_bits(bb[col])
                 q = rng.integers(0, 4, size=m)
                 d = rng.integers(0, 2, size=m)
-                b = b[rows[:, None], _TURN[q, d]]
-                alive &= ~(has_five(b, 1) | has_five(b, 2))
-            good = b[alive]
-            got.append(good[:need])
-            need -= len(got[-1])
+                bb[0] = _turn_bits(bb[0], q, d)
+                bb[1] = _turn_bits(bb[1], q, d)
+                alive &= ~(_five_bits(bb[0]) | _five_bits(bb[1]))
+            keep = np.nonzero(alive)[0][:need]
+            b = np.zeros((len(keep), 36), np.uint8)
+            b[((bb[0][keep, None] >> cells) & 1) == 1] = 1
+            b[((bb[1][keep, None] >> cells) & 1) == 1] = 2
+            got.append(b)
+            need -= len(keep)
         out[want] = np.concatenate(got)
     return out
 
