@@ -206,13 +206,16 @@ int pentago_serve_create(const pentago_serve_config *cfg, pentago_server **out);
 
 /* Register a resident solved section (device table, borrowed until destroy).
  * Queries whose quadrant counts match a resident section are answered by
- * lookup (Section VIII: positions inside the database are read, not solved). */
+ * lookup (Section VIII: positions inside the database are read, not solved).
+ * EINVAL while queries are in flight: register sections first. */
 int pentago_serve_add_section(pentago_server *srv, pentago_section s,
                               const pentago_superinfo *table);
 
 /* Submit one board.  EAGAIN when max_inflight queries are pending; EINVAL
  * for an invalid board; ERANGE for more than 10 empty cells on a board that
- * no resident section holds. */
+ * no resident section holds.  A batch is admitted when a stream is idle and
+ * its device scratch fits memory_budget next to the batches running (a
+ * batch is always admitted when nothing runs, so no query waits forever). */
 int pentago_serve_submit(pentago_server *srv, pentago_board board, uint64_t *ticket);
 
 /* Fetch the result of a ticket into host memory.  EAGAIN while pending;
@@ -220,6 +223,16 @@ int pentago_serve_submit(pentago_server *srv, pentago_board board, uint64_t *tic
 int pentago_serve_poll(pentago_server *srv, uint64_t ticket, pentago_superinfo *out);
 
 int pentago_serve_stats_get(pentago_server *srv, pentago_serve_stats *stats);
+
+/* Clear the latency samples and counters (e.g. after a warm-up). */
+int pentago_serve_reset_stats(pentago_server *srv);
+
+/* Open-loop replay: submits boards[i] at arrival_s[i] seconds after the call
+ * starts (busy-waiting for each arrival, retrying while the server answers
+ * EAGAIN) and collects every result into results[i] (host) from a second
+ * thread.  Returns when all results are in. */
+int pentago_serve_replay(pentago_server *srv, const pentago_board *boards, const double *arrival_s,
+                         size_t n, pentago_superinfo *results);
 
 /* Stop the server thread, wait for the device, release everything. */
 int pentago_serve_destroy(pentago_server *srv);

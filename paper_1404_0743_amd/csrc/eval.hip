@@ -77,6 +77,31 @@ static int eval_alloc(size_t n, int grid, hipStream_t st, EvalAlloc *A)
     return 0;
 }
 
+// Scratch bytes of one endgame batch of n roots (deep: some root has 9 or
+// 10 empty cells and needs the global layer buffers).
+size_t eval_scratch_bytes(size_t n, int grid, bool deep)
+{
+    return (deep ? (size_t)grid * 2 * kDagGlobalLayer * 64 : 0) + 64 * 4 + 16 + n * 5 + 256;
+}
+
+// Enqueue one endgame batch on st with stream-ordered scratch.
+int eval_enqueue(const uint64_t *boards, size_t n, uint4 *out, int *status, bool deep, int grid,
+                 hipStream_t st)
+{
+    DevTables T;
+    int rc = device_tables(&T);
+    if (rc) return rc;
+    EvalAlloc A;
+    rc = eval_alloc(n, deep ? grid : 0, st, &A);
+    if (rc) return rc;
+    A.S.global_slots = grid;
+    hipError_t e = launch_eval_bin(boards, n, A.S, status, out, T, st);
+    if (e == hipSuccess) e = launch_eval_persistent(boards, n, out, A.S, grid, T, st);
+    (void)hipFreeAsync(A.base, st);
+    if (e != hipSuccess) return hip_fail(e, "eval launch");
+    return 0;
+}
+
 }  // namespace pg
 
 using namespace pg;

@@ -25,5 +25,9 @@ size_t prep_bytes(const SweepJob &J, int j);
 int run_job(SweepJob &J, const DevTables &T, hipStream_t st);
 int tuned_tile_lines(const SweepJob &J);
 void remember_tile_lines(const SweepJob &J, int G);
+int eval_grid(int *grid);
+size_t eval_scratch_bytes(size_t n, int grid, bool deep);
+int eval_enqueue(const uint64_t *boards, size_t n, uint4 *out, int *status, bool deep, int grid,
+                 hipStream_t st);
 
 }  // namespace pg

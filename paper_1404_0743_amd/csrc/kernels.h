@@ -82,6 +82,14 @@ hipError_t launch_eval_group(const uint64_t *boards, int e, int first, int count
                              const EvalScratch &S, const DevTables &T, hipStream_t s);
 
 int dag_lds_bytes(int e);
+
+// A solved section kept resident for lookups.
+struct ResidentSection {
+    const uint4 *table;
+    int m[4];
+};
+hipError_t launch_lookup(const uint64_t *boards, const int *sec_of, int n,
+                         const ResidentSection *secs, uint4 *out, const DevTables &T, hipStream_t s);
 // Dynamic LDS of one sweep tile: G lines of mD parents, child lines of cmD
 // entries (cmD = 0 when the staged dimension has no children).
 int sweep_lds_bytes(int G, int mD, int cmD);

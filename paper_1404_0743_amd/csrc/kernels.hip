@@ -955,6 +955,44 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// Resident-section lookup (Section VIII: positions inside the database are
+// read, not solved): each quadrant of the query is turned to its
+// rotation-minimal pattern (k_j turns), the entry is read and shifted back by
+// k_j along every dimension.
+__global__ void __launch_bounds__(256)
+    lookup_kernel(const uint64_t *boards, const int *sec_of, int n, const ResidentSection *secs,
+                  uint4 *out, DevTables T)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t b = boards[i];
+    const ResidentSection S = secs[sec_of[i]];
+    int idx[4], k[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint16_t cc = T.canon[(b >> (16 * j)) & 0xffff];
+        idx[j] = cc & 0xfff;
+        k[j] = cc >> 12;
+    }
+    Set256 W, N;
+    load_info(S.table + 4 * block_offset(S.m, idx), W, N);
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        W = shift_dim(W, j, k[j]);
+        N = shift_dim(N, j, k[j]);
+    }
+    store_info(out + 4 * (size_t)i, W, N);
+}
+
+hipError_t launch_lookup(const uint64_t *boards, const int *sec_of, int n,
+                         const ResidentSection *secs, uint4 *out, const DevTables &T, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(lookup_kernel, dim3((n + 255) / 256), dim3(256), 0, s, boards, sec_of, n,
+                       secs, out, T);
+    return hipGetLastError();
+}
+
 hipError_t launch_eval_bin(const uint64_t *boards, size_t n, const EvalScratch &S, int *status,
                            uint4 *out, const DevTables &T, hipStream_t s)
 {

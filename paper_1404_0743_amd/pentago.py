@@ -75,6 +75,8 @@ _SIGS = {
     "pentago_serve_poll": ([_P, ctypes.c_uint64, _P], ctypes.c_int),
     "pentago_serve_stats_get": ([_P, _P], ctypes.c_int),
     "pentago_serve_destroy": ([_P], ctypes.c_int),
+    "pentago_serve_reset_stats": ([_P], ctypes.c_int),
+    "pentago_serve_replay": ([_P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "pentago_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "pentago_last_error": ([], ctypes.c_char_p),
     "pentago_debug_five": ([Board, ctypes.c_int, _P], ctypes.c_int),
@@ -309,6 +311,20 @@ class Server:
         s = ServeStats()
         _check(lib().pentago_serve_stats_get(self.h, ctypes.byref(s)), "pentago_serve_stats_get")
         return {k: getattr(s, k) for k, _ in ServeStats._fields_}
+
+    def reset_stats(self):
+        _check(lib().pentago_serve_reset_stats(self.h), "pentago_serve_reset_stats")
+
+    def replay(self, codes, arrival_s):
+        """Open-loop replay of (n, 4) quadrant codes at the given arrival
+        times (seconds); returns (n, 8) uint64 results."""
+        codes = np.ascontiguousarray(codes, dtype=np.uint16).reshape(-1, 4)
+        t = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        out = np.zeros((len(codes), 8), np.uint64)
+        _check(lib().pentago_serve_replay(self.h, codes.ctypes.data_as(ctypes.c_void_p),
+                                          t.ctypes.data_as(ctypes.c_void_p), len(codes),
+                                          out.ctypes.data_as(ctypes.c_void_p)), "pentago_serve_replay")
+        return out
 
     def close(self):
         if self.h:

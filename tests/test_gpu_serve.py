@@ -1,0 +1,132 @@
+"""GPU tests of the query server (pentago_serve_*): every answer, looked up
+in a resident section or searched on the device, equals the oracle's minimax
+table of the query board; each answer is the same alone and in a mixed
+stream; a tiny memory budget still answers everything; the in-flight bound
+gives EAGAIN."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1404_0743_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1404_0743_amd import pentago
+    pentago.lib()
+    return pentago
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+RESIDENT = ((7, 2), (2, 7), (1, 7), (8, 1))   # 35 stones, solved on the GPU
+
+
+@pytest.fixture(scope="module")
+def resident(P):
+    child = O.child_counts(RESIDENT, 2)
+    ct = torch.empty((O.section_entries(child), 8), dtype=torch.int64, device="cuda")
+    P.pentago_solve_section(child, [None] * 4, ct)
+    t = torch.empty((O.section_entries(RESIDENT), 8), dtype=torch.int64, device="cuda")
+    P.pentago_solve_section(RESIDENT, [None, None, ct, None], t)
+    torch.cuda.synchronize()
+    return t
+
+
+def queries(n_lookup, n_search, seed):
+    """Lookups: boards of the resident section, each quadrant turned at random
+    (so the server must canonicalise); searches: random-play boards."""
+    rng = np.random.default_rng(seed)
+    shape = O.section_shape(RESIDENT)
+    look = []
+    for _ in range(n_lookup):
+        b = O.section_board(RESIDENT, [rng.integers(0, m) for m in shape])
+        look.append(O.apply(b, int(rng.integers(0, 256))))
+    search = I.random_play_boards(n_search, 29, 34, seed=seed)
+    boards = np.concatenate([np.array(look).reshape(-1, 36), search])
+    perm = rng.permutation(len(boards))
+    return boards[perm]
+
+
+def run_all(P, srv, codes):
+    """Submit everything (waiting on the oldest ticket whenever the server
+    answers EAGAIN), then collect the results in order."""
+    tickets, out, done = [], {}, 0
+    for c in codes:
+        while True:
+            t = srv.submit(c)
+            if t is not None:
+                tickets.append(t)
+                break
+            r = srv.poll(tickets[done])
+            if r is not None:
+                out[done] = r
+                done += 1
+    for i in range(done, len(tickets)):
+        while True:
+            r = srv.poll(tickets[i])
+            if r is not None:
+                out[i] = r
+                break
+    return np.array([out[i] for i in range(len(tickets))])
+
+
+def test_answers_match_oracle_alone_and_mixed(P, resident):
+    log("serve mixed")
+    boards = queries(120, 200, seed=3)
+    codes = P.boards_to_codes(boards)
+    srv = P.Server(memory_budget=1 << 30, max_inflight=4096, max_batch=64, streams=3)
+    srv.add_section(RESIDENT, resident)
+    mixed = run_all(P, srv, codes)
+    st = srv.stats()
+    assert st["queries"] == len(boards) and st["lookups"] == 120 and st["searches"] == 200
+    assert st["p50_us"] > 0 and st["p99_us"] >= st["p50_us"]
+    alone = np.array([run_all(P, srv, codes[i:i + 1])[0] for i in range(0, len(codes), 7)])
+    assert np.array_equal(alone, mixed[::7])
+    srv.close()
+    want = O.minimax_tables(boards)
+    assert np.array_equal(mixed, want)
+
+
+def test_tiny_budget_and_backpressure(P, resident):
+    log("serve budget")
+    boards = queries(10, 60, seed=4)
+    codes = P.boards_to_codes(boards)
+    srv = P.Server(memory_budget=1, max_inflight=16, max_batch=8, streams=2)
+    srv.add_section(RESIDENT, resident)
+    tickets, got = [], {}
+    for c in codes[:16]:
+        tickets.append(srv.submit(c))
+    assert all(t is not None for t in tickets)
+    assert srv.submit(codes[16]) is None          # 16 in flight: EAGAIN
+    for t in tickets:
+        while srv.poll(t) is None:
+            pass
+    res = run_all(P, srv, codes)
+    srv.close()
+    assert np.array_equal(res, O.minimax_tables(boards))
+
+
+def test_replay_open_loop(P, resident):
+    log("serve replay")
+    boards = queries(50, 150, seed=5)
+    codes = P.boards_to_codes(boards)
+    srv = P.Server(memory_budget=1 << 30, max_inflight=4096, max_batch=64, streams=2)
+    srv.add_section(RESIDENT, resident)
+    arrivals = I.poisson_arrivals(len(codes), rate=20000.0, seed=6)
+    res = srv.replay(codes, arrivals)
+    st = srv.stats()
+    srv.close()
+    assert st["queries"] == len(codes)
+    assert np.array_equal(res, O.minimax_tables(boards))
