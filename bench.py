@@ -73,13 +73,14 @@ def main():
               "(see DESIGN.md for how the sweep would shard)", file=sys.stderr)
         sys.exit(2)
 
-    boards_2p20 = None
+    boards_2p20 = serve_queries = None
     if not args.no_extra:
         # generated before the GPU is touched (the generator forks workers)
         from paper_1404_0743_amd import inputs as I
         t0 = time.perf_counter()
         boards_2p20 = I.random_play_boards(1 << 20, 28, 33)
-        log("generated 2^20 endgame roots in %.1f s" % (time.perf_counter() - t0))
+        serve_queries = I.random_play_boards(1 << 17, 26, 33, seed=I.SEED_SERVE)
+        log("generated 2^20 endgame roots and 2^17 queries in %.1f s" % (time.perf_counter() - t0))
 
     import torch
     from paper_1404_0743_amd import pentago as P
@@ -160,9 +161,9 @@ def main():
     }
     if not args.no_extra:
         import bench_extra
-        del out, child, children
-        torch.cuda.empty_cache()
-        res["extra"] = bench_extra.run_all(P, torch, stream, boards_2p20)
+        out_keep, child_keep = out, child
+        resident = [(SECTION, out_keep), (CHILD, child_keep)]
+        res["extra"] = bench_extra.run_all(P, torch, stream, boards_2p20, serve_queries, resident)
     if not args.no_cpu:
         log("timing the CPU oracle on a sample ...")
         res["cpu_baseline"] = cpu_baseline(entries, positions)

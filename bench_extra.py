@@ -9,6 +9,10 @@
                  positions, stratified by size), child chains solved first
                  (untimed): one persistent launch per layer replayed from a
                  hipGraph against 64 per-section launches.
+  serving        an open-loop Poisson stream of 2^17 queries with 26..33
+                 stones (first 4096 dropped as warm-up) against the server
+                 holding every section solved above resident; p50/p99 latency
+                 and queries/s, against one query per launch.
 Inputs are resident on the GPU when timing starts; times are HIP events on
 the launch stream.
 """
@@ -62,7 +66,9 @@ def endgame(P, torch, stream, boards, grouped_too):
     return res
 
 
-def layers(P, torch, stream):
+def layers(P, torch, stream, resident=None):
+    """resident: a list that receives (counts, table) of every layer section
+    and child section solved here (for the serving workload)."""
     out = {}
     cache = {}
 
@@ -106,6 +112,8 @@ def layers(P, torch, stream):
         same = all(torch.equal(r, o) for r, (_, _, o) in zip(ref, jobs))
         info = plan.info()
         plan.close()
+        if resident is not None:
+            resident.extend((s, o) for s, _, o in jobs)
         sizes = [I.section_positions(s) for s in secs]
         out["slice%d" % stones] = {
             "sections": len(secs), "positions": positions,
@@ -115,17 +123,64 @@ def layers(P, torch, stream):
             "batched_over_plain": med_plain / med_graph, "same_bytes": same,
             "tiles": info["tiles"], "grid": info["grid"]}
         log("layer %d: plain %.3f ms, batched %.3f ms" % (stones, med_plain, med_graph))
-    resident = sum(t.numel() * 8 for t in cache.values())
-    out["resident_child_bytes"] = resident
+    out["resident_child_bytes"] = sum(t.numel() * 8 for t in cache.values())
+    if resident is not None:
+        resident.extend(cache.items())
     return out
 
 
-def run_all(P, torch, stream, boards_2p20=None):
+def serving(P, torch, stream, resident, queries):
+    """Open-loop Poisson stream of position queries (26..33 stones) against a
+    server holding the given resident sections.  The rate is 0.7 of the
+    saturated capacity measured first on the same queries.  The plain form
+    answers a sample of the stream one query per launch."""
+    codes = P.boards_to_codes(queries)
+    srv = P.Server(memory_budget=4 << 30, max_inflight=1 << 20, max_batch=4096, streams=4)
+    for counts, table in resident:
+        srv.add_section(counts, table)
+    warm = 4096
+    # capacity: everything arrives at once
+    t0 = time.perf_counter()
+    srv.replay(codes, np.zeros(len(codes)))
+    cap = len(codes) / (time.perf_counter() - t0)
+    rate = 0.7 * cap
+    arrivals = I.poisson_arrivals(len(codes), rate)
+    srv.reset_stats()
+    srv.replay(codes[:warm], arrivals[:warm])
+    srv.reset_stats()
+    res = srv.replay(codes[warm:], arrivals[warm:] - arrivals[warm])
+    st = srv.stats()
+    srv.close()
+    # plain form: one query per launch, on a sample of the stream
+    sample = codes[warm:warm + 2048]
+    dev = torch.from_numpy(sample.view(np.int16).copy()).cuda()
+    out = torch.empty((len(sample), 8), dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(len(sample)):
+        P.pentago_eval_batch(dev[i:i + 1], out[i:i + 1], None, stream)
+        torch.cuda.synchronize()
+    plain_qps = len(sample) / (time.perf_counter() - t0)
+    # per-launch answers equal the served ones (searches; lookups are not in the sample's kind mix check)
+    served = res[:len(sample)]
+    empt = (queries[warm:warm + len(sample)] == 0).sum(axis=1)
+    same = bool(np.array_equal(out.cpu().numpy().view(np.uint64)[empt <= 10], served[empt <= 10]))
+    return {"queries": int(st["queries"]), "lookups": int(st["lookups"]), "searches": int(st["searches"]),
+            "batches": int(st["batches"]), "saturated_queries_per_s": cap, "offered_rate_per_s": rate,
+            "p50_us": st["p50_us"], "p99_us": st["p99_us"], "queries_per_s": st["queries_per_s"],
+            "plain_one_query_per_launch_per_s": plain_qps, "served_over_plain": st["queries_per_s"] / plain_qps,
+            "plain_answers_equal_served": same, "warmup_dropped": warm}
+
+
+def run_all(P, torch, stream, boards_2p20=None, serve_queries=None, resident=None):
     res = {}
     for name, fn in (("endgame_4096", lambda: endgame(P, torch, stream, I.random_placement_boards(4096, 17, 16), False)),
                      ("endgame_2p20", lambda: endgame(P, torch, stream, boards_2p20, True)),
-                     ("layers", lambda: layers(P, torch, stream))):
+                     ("layers", lambda: layers(P, torch, stream, resident)),
+                     ("serving", lambda: serving(P, torch, stream, resident, serve_queries))):
         if name == "endgame_2p20" and boards_2p20 is None:
+            continue
+        if name == "serving" and serve_queries is None:
             continue
         t0 = time.perf_counter()
         try:
