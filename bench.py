@@ -69,8 +69,8 @@ def main():
                     help="also run a plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the sweep would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: sharding the sweep over several GPUs "
+              "is not implemented", file=sys.stderr)
         sys.exit(2)
 
     boards_2p20 = serve_queries = None
@@ -100,7 +100,7 @@ def main():
     terminal_ms = t0.elapsed_time(t1)
     children = [None, None, None, child]
     # tile shape picked by the library's autotuner (setup, not timed)
-    tile_lines, tune_ms = P.pentago_autotune_section(SECTION, children, out, stream)
+    tile_lines, tile_threads, tune_ms = P.pentago_autotune_section(SECTION, children, out, stream)
 
     for _ in range(args.warmup):
         P.pentago_solve_section(SECTION, children, out, stream)
@@ -153,7 +153,7 @@ def main():
                                "white to move, %d entries, %d positions, child section "
                                "(5,4),(4,5),(5,4),(4,5) %d entries resident" % (entries, positions, centries),
                    "entries": entries, "positions": positions, "shape": list(shape),
-                   "tile_lines": tile_lines},
+                   "tile_lines": tile_lines, "tile_threads": tile_threads},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "kernel_ms": {"sweep_avg": avg_ms, "sweep_min": float(np.min(kernel_ms)),

@@ -113,14 +113,16 @@ int pentago_child_section(pentago_section s, int j, pentago_section *child);
 int pentago_solve_section(pentago_section s, const pentago_superinfo *const child[4],
                           pentago_superinfo *out, void *hip_stream);
 
-/* The tile autotuner: times every tile shape the section admits (lines per
- * tile, see DESIGN) with HIP events on hip_stream, remembers the fastest for
- * this section geometry (later pentago_solve_section / pentago_solve_sections
- * calls with the same geometry use it) and leaves out holding the sweep's
- * result.  Synchronises the stream.  tile_lines and best_ms may be NULL. */
+/* The tile autotuner: times every tile shape the section admits (lines of
+ * the section along the staged quadrant per tile, and workgroup size 256 or
+ * 512) with HIP events on hip_stream, remembers the fastest for this section
+ * geometry (later pentago_solve_section calls with the same geometry use it;
+ * pentago_solve_sections uses its lines per tile) and leaves out holding the
+ * sweep's result.  Synchronises the stream.  tile_lines, tile_threads and
+ * best_ms may be NULL. */
 int pentago_autotune_section(pentago_section s, const pentago_superinfo *const child[4],
                              pentago_superinfo *out, void *hip_stream, int *tile_lines,
-                             float *best_ms);
+                             int *tile_threads, float *best_ms);
 
 /* One section of a batch: its counts, its four child tables as for
  * pentago_solve_section, and its output. */

@@ -165,9 +165,10 @@ void section_shape_of(const pentago_section &s, int m[4])
 }
 
 // Build the sweep job of one section.  `force_d` >= 0 picks the staged
-// dimension; G > 0 the lines per tile (both for the tile autotuner).
+// dimension; G > 0 the lines per tile and force_threads > 0 the workgroup
+// size (for the tile autotuner).
 int make_job(const pentago_section &s, const pentago_superinfo *const child[4],
-             pentago_superinfo *out, SweepJob *J, int force_d, int forceG)
+             pentago_superinfo *out, SweepJob *J, int force_d, int forceG, int force_threads)
 {
     if (!section_valid(s)) return fail(PENTAGO_EINVAL, "invalid section counts");
     if (!out) return fail(PENTAGO_EINVAL, "out is NULL");
@@ -215,8 +216,10 @@ int make_job(const pentago_section &s, const pentago_superinfo *const child[4],
     // tile in one pass of its 256 threads when the child line allows, and the
     // tile's LDS within 64 KiB
     int G = 8;
+    const TileShape tuned = tuned_tile_shape(*J);
+    J->threads = force_threads > 0 ? force_threads : tuned.lines > 0 ? tuned.threads : 256;
     if (forceG > 0) G = forceG;
-    else if (int tuned = tuned_tile_lines(*J)) G = tuned;
+    else if (tuned.lines > 0) G = tuned.lines;
     else {
         // (the kernels give every line 8 slots per position when D == 3,
         // so a smaller G only helps the child pass for D == 3)

@@ -20,11 +20,16 @@ pentago_section child_of(const pentago_section &s, int j);
 void section_shape_of(const pentago_section &s, int m[4]);
 uint64_t host_block_offset(const int *m, const int *idx);
 int make_job(const pentago_section &s, const pentago_superinfo *const child[4],
-             pentago_superinfo *out, SweepJob *J, int force_d, int forceG);
+             pentago_superinfo *out, SweepJob *J, int force_d, int forceG, int force_threads = 0);
 size_t prep_bytes(const SweepJob &J, int j);
 int run_job(SweepJob &J, const DevTables &T, hipStream_t st);
-int tuned_tile_lines(const SweepJob &J);
-void remember_tile_lines(const SweepJob &J, int G);
+// Tile shape of a section geometry chosen by the autotuner (0 lines: none).
+struct TileShape {
+    int lines;
+    int threads;
+};
+TileShape tuned_tile_shape(const SweepJob &J);
+void remember_tile_shape(const SweepJob &J, TileShape t);
 int eval_grid(int *grid);
 size_t eval_scratch_bytes(size_t n, int grid, bool deep);
 int eval_enqueue(const uint64_t *boards, size_t n, uint4 *out, int *status, bool deep, int grid,

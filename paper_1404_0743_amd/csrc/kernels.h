@@ -47,6 +47,7 @@ struct SweepJob {
     int o1, o2;        // the remaining two dimensions
     long long ntiles;
     int lds_bytes;     // dynamic LDS needed by one tile
+    int threads;       // workgroup size of the one-section sweep (256 or 512)
 };
 
 // Host launchers (kernels.hip).

@@ -127,7 +127,7 @@ __device__ __forceinline__ void child_entry_terms(const SweepJob &J, const DevTa
     child_terms(Fc, W, N, A, B);
 }
 
-__device__ __forceinline__ Set256 lds_set(const uint4 *p)
+__device__ __forceinline__ Set256 set_from(const uint4 *p)
 {
     Set256 x;
     const uint4 u = p[0], v = p[1];
@@ -266,25 +266,99 @@ __device__ __forceinline__ Set256 five_lut(const uint2 *lut, const uint4 sel)
     return F;
 }
 
-// OR into acc the 8-word set at p shifted by k along internal dimension 3
-// (a re-addressing of the four word pairs).
-__device__ __forceinline__ void or_rotated(Set256 &acc, const uint32_t *p, int k)
+// ---------------------------------------------------------------------------
+// Quad form of the parent pass: the four lanes of a quad share one parent
+// entry, lane k owning word pair k (internal dimension 3 = turn k of the
+// staged quadrant D).  Every term of the recurrence is local to a word pair
+// except the exchange of dimensions D and 3, which becomes a data exchange
+// inside the quad (DPP quad permutations), and the final store, where the
+// quad writes the entry's 64 bytes as four contiguous 16-byte pieces.
+// ---------------------------------------------------------------------------
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t quad_perm(uint32_t x)
 {
-#pragma unroll
-    for (int g3 = 0; g3 < 4; g3++) {
-        const uint2 v = *(const uint2 *)(p + 2 * ((g3 - k) & 3));
-        acc.w[2 * g3] |= v.x;
-        acc.w[2 * g3 + 1] |= v.y;
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, true);
+}
+constexpr int kQuadXor1 = 0xB1;   // lanes [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;   // lanes [2,3,0,1]
+constexpr int kQuadEven = 0x88;   // lanes [0,2,0,2]
+constexpr int kQuadOdd = 0xDD;    // lanes [1,3,1,3]
+
+template <int LB>
+__device__ __forceinline__ uint32_t quad_partner(uint32_t x)
+{
+    return LB == 0 ? quad_perm<kQuadXor1>(x) : quad_perm<kQuadXor2>(x);
+}
+
+// Cross-lane swap_index_bits<I, LB + 1> on a set spread over a quad (lane k
+// holds words 2k and 2k+1, so word-index bit LB + 1 is lane bit LB).
+template <int I, int LB>
+__device__ __forceinline__ void quad_swap_bits(uint2 &x, int k)
+{
+    constexpr int s = 1 << I;
+    constexpr uint32_t M = I == 0 ? 0x55555555u : I == 1 ? 0x33333333u : I == 2 ? 0x0f0f0f0fu
+                         : I == 3 ? 0x00ff00ffu : 0x0000ffffu;
+    const bool hi = (k >> LB) & 1;
+    const uint32_t px = quad_partner<LB>(x.x), py = quad_partner<LB>(x.y);
+    uint32_t lo = hi ? px : x.x, up = hi ? x.x : px;
+    uint32_t t = ((lo >> s) ^ up) & M;
+    x.x = hi ? (up ^ t) : (lo ^ (t << s));
+    lo = hi ? py : x.y;
+    up = hi ? x.y : py;
+    t = ((lo >> s) ^ up) & M;
+    x.y = hi ? (up ^ t) : (lo ^ (t << s));
+}
+
+// swap_with3<D> on a set spread over a quad (self-inverse, as swap_with3).
+template <int D>
+__device__ __forceinline__ void quad_swap_with3(uint2 &x, int k)
+{
+    if constexpr (D == 3) {
+        return;
+    } else if constexpr (D == 2) {
+        quad_swap_bits<4, 1 - 1>(x, k);
+        // words 1 <-> 4 and 3 <-> 6: word-in-pair bit <-> lane bit 1
+        const uint32_t px = quad_perm<kQuadXor2>(x.x), py = quad_perm<kQuadXor2>(x.y);
+        if ((k >> 1) & 1) x.x = py;
+        else x.y = px;
+    } else {
+        quad_swap_bits<2 * D, 0>(x, k);
+        quad_swap_bits<2 * D + 1, 1>(x, k);
     }
+}
+
+// Word pair k of a five-set from the line's chunk tables (see five_lut).
+__device__ __forceinline__ uint2 five_pair(const uint2 *lut, uint32_t sel)
+{
+    const char *base = (const char *)lut;
+    const uint2 a = *(const uint2 *)(base + (sel & 1023u));
+    const uint2 b = *(const uint2 *)(base + ((sel >> 10) & 1023u));
+    const uint2 c = *(const uint2 *)(base + (sel >> 20));
+    return make_uint2(a.x | b.x | c.x, a.y | b.y | c.y);
+}
+
+// shift_dim restricted to one word pair, for dimensions 0..2 (which never
+// move bits between word pairs).
+__device__ __forceinline__ uint2 shift_pair(uint2 x, int d, int k)
+{
+    Set256 t;
+    t.w[0] = x.x;
+    t.w[1] = x.y;
+#pragma unroll
+    for (int i = 2; i < 8; i++) t.w[i] = 0;
+    const Set256 r = shift_dim(t, d, k);
+    return make_uint2(r.w[0], r.w[1]);
 }
 
 // Children of one parent along a dimension JD that is not staged: their
 // A/B terms were prepared per child entry by prep_kernel, in the parent's
 // internal layout (64 B each, in the child section's blocked order).
+// In the quad parent pass lane k reads word pair k of each prepared term.
 template <int D, int JD>
-__device__ __forceinline__ void direct_children(const SweepJob &J, const DevTables &T,
-                                                const Idx4 &idx, const QInfo &q, Set256 &Wnt,
-                                                Set256 &Nnt)
+__device__ __forceinline__ void direct_children_pair(const SweepJob &J, const DevTables &T,
+                                                     const Idx4 &idx, const QInfo &q, int k,
+                                                     uint2 &Wnt, uint2 &Nnt)
 {
     int cshape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
     cshape[JD] = J.cm[JD];
@@ -296,9 +370,11 @@ __device__ __forceinline__ void direct_children(const SweepJob &J, const DevTabl
         const uint16_t cc = T.canon[q.code + J.mover * c_pow3[cell]];
         Idx4 cidx = idx;
         cidx.v[JD] = cc & 0xfff;
-        const uint4 *p = J.prep[JD] + 4 * block_offset(cshape, cidx.v);
-        s_or_into(Wnt, shift_dim(lds_set(p), ip, cc >> 12));
-        s_or_into(Nnt, shift_dim(lds_set(p + 2), ip, cc >> 12));
+        const uint2 *p = (const uint2 *)(J.prep[JD] + 4 * block_offset(cshape, cidx.v));
+        const uint2 a = shift_pair(p[k], ip, cc >> 12);
+        const uint2 b = shift_pair(p[4 + k], ip, cc >> 12);
+        Wnt.x |= a.x; Wnt.y |= a.y;
+        Nnt.x |= b.x; Nnt.y |= b.y;
     }
 }
 
@@ -394,6 +470,26 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
     const int cmD = J.cm[D];
     const int mD = J.m[D];
     const TileLds L = tile_lds(lds_base, J.G, mD, staged ? cmD : 0);
+    // item it of the child pass -> (child position ic, line v): it / nlines
+    // by a 16-bit reciprocal, exact for it < 8 * 420 and nlines <= 8
+    const uint32_t rcp = (65536u + nlines - 1) / nlines;
+    const bool load_children = staged && !((J.odmask >> D) & 1);
+    int cshape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
+    cshape[D] = cmD;
+
+    // The first child item of this thread is fetched from HBM now, so its
+    // latency overlaps the table set-up below.
+    uint4 pre[4] = {};
+    if (load_children && (int)threadIdx.x < nlines * cmD) {
+        const int it = threadIdx.x;
+        const int ic = (int)(((uint32_t)it * rcp) >> 16);
+        Idx4 idx = base;
+        set4(idx, J.e, get4(base, J.e) + (it - ic * nlines));
+        idx.v[D] = ic;
+        const uint4 *p = J.child[D] + 4 * block_offset(cshape, idx.v);
+#pragma unroll
+        for (int i = 0; i < 4; i++) pre[i] = p[i];
+    }
 
     // Phase 0: per-line tables (LineMasks of the fixed quadrants, partial
     // sets, chunk tables), for both colours.  Work items are kept small and
@@ -483,17 +579,13 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
     // Phase 1: stage the child line(s) of dimension D (Fig. 3 "gather"):
     // A = F_c(child) | rmax(not N_child), B = F_c(child) | rmax(not W_child).
     if (staged) {
-        // item it -> (child position ic, line v): it / nlines by a 16-bit
-        // reciprocal, exact for it < 8 * 420 and nlines <= 8
         const int total = nlines * cmD;
-        const uint32_t rcp = (65536u + nlines - 1) / nlines;
-        for (int it = threadIdx.x; it < total; it += blockDim.x) {
+        auto child_item = [&](int it, Set256 W, Set256 N) {
             const int ic = (int)(((uint32_t)it * rcp) >> 16);
             const int v = it - ic * nlines;
-            const ChildPosRec cp = L.cpos[ic];
+            const ChildPosRec &cp = L.cpos[ic];
             const uint2 *lut = L.lut + kLutStride * v;
             const Set256 Fc = five_lut(lut + 192 * (c - 1), cp.sel_c);
-            Set256 W, N;
             if ((J.odmask >> D) & 1) {
                 const Set256 Fo = five_lut(lut + 192 * (2 - c), cp.sel_o);
 #pragma unroll
@@ -502,12 +594,6 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
                     N.w[i] = Fo.w[i] | ~Fc.w[i];
                 }
             } else {
-                Idx4 idx = base;
-                set4(idx, J.e, get4(base, J.e) + v);
-                idx.v[D] = ic;
-                int cshape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
-                cshape[D] = cmD;
-                load_info(J.child[D] + 4 * block_offset(cshape, idx.v), W, N);
                 swap_with3<D>(W);
                 swap_with3<D>(N);
             }
@@ -519,65 +605,97 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
                 *(uint2 *)(r + i) = make_uint2(A.w[i], A.w[i + 1]);
                 *(uint2 *)(r + 8 + i) = make_uint2(B.w[i], B.w[i + 1]);
             }
+        };
+        // the first item of each thread uses the prefetched entry
+        if ((int)threadIdx.x < total) child_item(threadIdx.x, set_from(pre), set_from(pre + 2));
+        for (int it = threadIdx.x + blockDim.x; it < total; it += blockDim.x) {
+            Set256 W, N;
+            if (load_children) {
+                const int ic = (int)(((uint32_t)it * rcp) >> 16);
+                Idx4 idx = base;
+                set4(idx, J.e, get4(base, J.e) + (it - ic * nlines));
+                idx.v[D] = ic;
+                load_info(J.child[D] + 4 * block_offset(cshape, idx.v), W, N);
+            } else {
+                W = s_zero();
+                N = s_zero();
+            }
+            child_item(it, W, N);
         }
         __syncthreads();
     }
 
-    // Phase 2: every parent entry of the tile (Fig. 3 "compute").
-    // slots: 8 per line per position along D (memory order inside a block:
-    // for D = 3 the line r2 is slower and r3 faster), unused slots skipped
-    const int total = D == 3 ? 64 * ((mD + 7) >> 3) : 8 * mD;
-    for (int it = threadIdx.x; it < total; it += blockDim.x) {
-        int v, iD;
-        if (D == 3) {
-            v = (it >> 3) & 7;
-            iD = 8 * (it >> 6) + (it & 7);
-        } else {
-            v = it & 7;
-            iD = it >> 3;
-        }
-        if (v >= nlines || iD >= mD) continue;
-        Idx4 idx = base;
-        set4(idx, J.e, get4(base, J.e) + v);
-        idx.v[D] = iD;
+    // Phase 2: every parent entry of the tile (Fig. 3 "compute"), one quad
+    // of lanes per parent, lane k computing word pair k (turn k of D in the
+    // internal layout).  Parents run along the memory order of a block: for
+    // D = 3 consecutive quads take consecutive positions along D (the
+    // fastest index), otherwise consecutive lines (dimension 3).
+    const int k = threadIdx.x & 3;
+    const int nparents = nlines * mD;
+    // pi / div as a multiply-high by ceil(2^32 / div): exact for pi < 2^32 / div
+    // (pi < 8 * 420 here); div = 1 has no 32-bit multiplier and is kept apart
+    const uint32_t div = D == 3 ? (uint32_t)mD : (uint32_t)nlines;
+    const uint32_t magic = div > 1 ? 0xffffffffu / div + 1u : 0u;
+    const int shape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
+    for (int it = threadIdx.x; it < 4 * ((nparents + 15) & ~15); it += blockDim.x) {
+        const int pi0 = it >> 2;
+        const bool ok = pi0 < nparents;
+        const int pi = ok ? pi0 : nparents - 1;  // a padding quad repeats the last parent
+        const int hiq = div > 1 ? (int)__umulhi((uint32_t)pi, magic) : pi;
+        const int loq = pi - hiq * (int)div;
+        const int v = D == 3 ? hiq : loq;
+        const int iD = D == 3 ? loq : hiq;
         const PosRec &pr = L.pos[iD];
-
-        Set256 Wnt = s_zero(), Nnt = s_zero();
-        if (J.emask == 0) Nnt = s_full();
+        uint2 Wnt = make_uint2(0, 0);
+        uint2 Nnt = J.emask == 0 ? make_uint2(0xffffffffu, 0xffffffffu) : make_uint2(0, 0);
         if (staged) {
             const uint32_t *line = L.rec + kRecWords * (v * cmD);
             const int n = pr.nchild;
             for (int e = 0; e < n; e++) {
                 const uint16_t cc = pr.child[e];
-                const uint32_t *r = line + kRecWords * (cc & 0xfff);
-                or_rotated(Wnt, r, cc >> 12);
-                or_rotated(Nnt, r + 8, cc >> 12);
+                const uint32_t *r = line + kRecWords * (cc & 0xfff) + 2 * ((k - (cc >> 12)) & 3);
+                const uint2 a = *(const uint2 *)r, b = *(const uint2 *)(r + 8);
+                Wnt.x |= a.x; Wnt.y |= a.y;
+                Nnt.x |= b.x; Nnt.y |= b.y;
             }
         }
+        Idx4 idx = base;
+        set4(idx, J.e, get4(base, J.e) + v);
+        idx.v[D] = iD;
         // Children along the other dimensions with empty cells.
         if (J.emask & ~(1 << D)) {
             QInfo q[4];
 #pragma unroll
             for (int j = 0; j < 4; j++) q[j] = T.qinfo[J.qb[j] + idx.v[j]];
-            if (D != 0 && (J.emask & 1)) direct_children<D, 0>(J, T, idx, q[0], Wnt, Nnt);
-            if (D != 1 && (J.emask & 2)) direct_children<D, 1>(J, T, idx, q[1], Wnt, Nnt);
-            if (D != 2 && (J.emask & 4)) direct_children<D, 2>(J, T, idx, q[2], Wnt, Nnt);
-            if (D != 3 && (J.emask & 8)) direct_children<D, 3>(J, T, idx, q[3], Wnt, Nnt);
+            if (D != 0 && (J.emask & 1)) direct_children_pair<D, 0>(J, T, idx, q[0], k, Wnt, Nnt);
+            if (D != 1 && (J.emask & 2)) direct_children_pair<D, 1>(J, T, idx, q[1], k, Wnt, Nnt);
+            if (D != 2 && (J.emask & 4)) direct_children_pair<D, 2>(J, T, idx, q[2], k, Wnt, Nnt);
+            if (D != 3 && (J.emask & 8)) direct_children_pair<D, 3>(J, T, idx, q[3], k, Wnt, Nnt);
         }
         const uint2 *lut = L.lut + kLutStride * v;
-        const Set256 Fc = five_lut(lut + 192 * (c - 1), pr.sel_c);
-        const Set256 Fo = five_lut(lut + 192 * (2 - c), pr.sel_o);
-        Set256 W, N;
-        combine(Fc, Fo, Wnt, Nnt, W, N);
-        swap_with3<D>(W);
-        swap_with3<D>(N);
-        const int shape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
-        store_info(J.out + 4 * block_offset(shape, idx.v), W, N);
+        const uint2 Fc = five_pair(lut + 192 * (c - 1), ((const uint32_t *)&pr.sel_c)[k]);
+        const uint2 Fo = five_pair(lut + 192 * (2 - c), ((const uint32_t *)&pr.sel_o)[k]);
+        uint2 W, N;
+        W.x = ~Fo.x & (Fc.x | Wnt.x);
+        W.y = ~Fo.y & (Fc.y | Wnt.y);
+        N.x = Fc.x | (~Fo.x & Nnt.x);
+        N.y = Fc.y | (~Fo.y & Nnt.y);
+        quad_swap_with3<D>(W, k);
+        quad_swap_with3<D>(N, k);
+        // lane j of the quad stores dwords 4j..4j+3 of the entry: W pairs
+        // (0,1), W pairs (2,3), N pairs (0,1), N pairs (2,3)
+        const uint32_t we0 = quad_perm<kQuadEven>(W.x), we1 = quad_perm<kQuadEven>(W.y);
+        const uint32_t wo0 = quad_perm<kQuadOdd>(W.x), wo1 = quad_perm<kQuadOdd>(W.y);
+        const uint32_t ne0 = quad_perm<kQuadEven>(N.x), ne1 = quad_perm<kQuadEven>(N.y);
+        const uint32_t no0 = quad_perm<kQuadOdd>(N.x), no1 = quad_perm<kQuadOdd>(N.y);
+        const bool isw = k < 2;
+        const uint4 piece = make_uint4(isw ? we0 : ne0, isw ? we1 : ne1, isw ? wo0 : no0, isw ? wo1 : no1);
+        if (ok) J.out[4 * block_offset(shape, idx.v) + k] = piece;
     }
 }
 
-template <int D>
-__global__ void __launch_bounds__(256) sweep_kernel(SweepJob J, DevTables T)
+template <int D, int NT>
+__global__ void __launch_bounds__(NT, NT == 512 ? 6 : 1) sweep_kernel(SweepJob J, DevTables T)
 {
     extern __shared__ uint4 lds[];
     sweep_tile<D>(J, T, blockIdx.x, (void *)lds);
@@ -639,12 +757,23 @@ hipError_t launch_prep(const SweepJob &job, int j, const DevTables &T, hipStream
 hipError_t launch_sweep(const SweepJob &job, const DevTables &T, hipStream_t s)
 {
     if (job.ntiles == 0) return hipSuccess;
-    const dim3 grid((unsigned)job.ntiles), block(256);
-    switch (job.d) {
-    case 0: hipLaunchKernelGGL(sweep_kernel<0>, grid, block, job.lds_bytes, s, job, T); break;
-    case 1: hipLaunchKernelGGL(sweep_kernel<1>, grid, block, job.lds_bytes, s, job, T); break;
-    case 2: hipLaunchKernelGGL(sweep_kernel<2>, grid, block, job.lds_bytes, s, job, T); break;
-    default: hipLaunchKernelGGL(sweep_kernel<3>, grid, block, job.lds_bytes, s, job, T); break;
+    const dim3 grid((unsigned)job.ntiles), block(job.threads);
+    if (job.threads == 512) {
+        switch (job.d) {
+        case 0: hipLaunchKernelGGL((sweep_kernel<0, 512>), grid, block, job.lds_bytes, s, job, T); break;
+        case 1: hipLaunchKernelGGL((sweep_kernel<1, 512>), grid, block, job.lds_bytes, s, job, T); break;
+        case 2: hipLaunchKernelGGL((sweep_kernel<2, 512>), grid, block, job.lds_bytes, s, job, T); break;
+        default: hipLaunchKernelGGL((sweep_kernel<3, 512>), grid, block, job.lds_bytes, s, job, T); break;
+        }
+    } else if (job.threads == 256) {
+        switch (job.d) {
+        case 0: hipLaunchKernelGGL((sweep_kernel<0, 256>), grid, block, job.lds_bytes, s, job, T); break;
+        case 1: hipLaunchKernelGGL((sweep_kernel<1, 256>), grid, block, job.lds_bytes, s, job, T); break;
+        case 2: hipLaunchKernelGGL((sweep_kernel<2, 256>), grid, block, job.lds_bytes, s, job, T); break;
+        default: hipLaunchKernelGGL((sweep_kernel<3, 256>), grid, block, job.lds_bytes, s, job, T); break;
+        }
+    } else {
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -14,24 +14,24 @@ namespace pg {
 
 using TileKey = std::tuple<int, int, int, int, int, int, int>;
 static std::mutex g_tune_mutex;
-static std::map<TileKey, int> g_tile_cache;
+static std::map<TileKey, TileShape> g_tile_cache;
 
 static TileKey tile_key(const SweepJob &J)
 {
     return TileKey(J.m[0], J.m[1], J.m[2], J.m[3], J.d, J.emask, J.cm[J.d]);
 }
 
-int tuned_tile_lines(const SweepJob &J)
+TileShape tuned_tile_shape(const SweepJob &J)
 {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     auto it = g_tile_cache.find(tile_key(J));
-    return it == g_tile_cache.end() ? 0 : it->second;
+    return it == g_tile_cache.end() ? TileShape{0, 0} : it->second;
 }
 
-void remember_tile_lines(const SweepJob &J, int G)
+void remember_tile_shape(const SweepJob &J, TileShape t)
 {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
-    g_tile_cache[tile_key(J)] = G;
+    g_tile_cache[tile_key(J)] = t;
 }
 
 // Launch prep passes and the sweep of one job (prep buffers stream-ordered).
@@ -59,7 +59,7 @@ using namespace pg;
 
 extern "C" int pentago_autotune_section(pentago_section s, const pentago_superinfo *const child[4],
                                         pentago_superinfo *out, void *hip_stream, int *tile_lines,
-                                        float *best_ms)
+                                        int *tile_threads, float *best_ms)
 {
     DevTables T;
     int rc = device_tables(&T);
@@ -71,39 +71,42 @@ extern "C" int pentago_autotune_section(pentago_section s, const pentago_superin
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
         return fail(PENTAGO_EDEVICE, "hipEventCreate");
-    int bestG = 0;
+    TileShape best_shape{0, 0};
     float best = 1e30f;
     const int cmd = (J0.emask >> J0.d) & 1 ? J0.cm[J0.d] : 0;
-    for (int G = 1; G <= 8 && rc == 0; G++) {
-        if (sweep_lds_bytes(G, J0.m[J0.d], cmd) > 65536) break;
-        SweepJob J;
-        rc = make_job(s, child, out, &J, -1, G);
-        if (rc) break;
-        rc = run_job(J, T, st);  // warm-up
-        float t = 1e30f;
-        for (int rep = 0; rep < 3 && rc == 0; rep++) {
-            (void)hipEventRecord(a, st);
-            rc = run_job(J, T, st);
-            (void)hipEventRecord(b, st);
-            if (hipEventSynchronize(b) != hipSuccess) rc = fail(PENTAGO_EDEVICE, "hipEventSynchronize");
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, a, b);
-            t = std::min(t, ms);
-        }
-        if (rc == 0 && t < best) {
-            best = t;
-            bestG = G;
+    for (int nt = 256; nt <= 512 && rc == 0; nt *= 2) {
+        for (int G = 1; G <= 8 && rc == 0; G++) {
+            if (sweep_lds_bytes(G, J0.m[J0.d], cmd) > 65536) break;
+            SweepJob J;
+            rc = make_job(s, child, out, &J, -1, G, nt);
+            if (rc) break;
+            rc = run_job(J, T, st);  // warm-up
+            float t = 1e30f;
+            for (int rep = 0; rep < 3 && rc == 0; rep++) {
+                (void)hipEventRecord(a, st);
+                rc = run_job(J, T, st);
+                (void)hipEventRecord(b, st);
+                if (hipEventSynchronize(b) != hipSuccess) rc = fail(PENTAGO_EDEVICE, "hipEventSynchronize");
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, a, b);
+                t = std::min(t, ms);
+            }
+            if (rc == 0 && t < best) {
+                best = t;
+                best_shape = TileShape{G, nt};
+            }
         }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (rc) return rc;
-    remember_tile_lines(J0, bestG);
+    remember_tile_shape(J0, best_shape);
     // leave out holding the result of the chosen shape
     SweepJob J;
-    rc = make_job(s, child, out, &J, -1, bestG);
+    rc = make_job(s, child, out, &J, -1, best_shape.lines, best_shape.threads);
     if (rc == 0) rc = run_job(J, T, st);
-    if (tile_lines) *tile_lines = bestG;
+    if (tile_lines) *tile_lines = best_shape.lines;
+    if (tile_threads) *tile_threads = best_shape.threads;
     if (best_ms) *best_ms = best;
     return rc;
 }

@@ -61,7 +61,7 @@ _SIGS = {
     "pentago_child_section": ([Section, ctypes.c_int, _P], ctypes.c_int),
     "pentago_solve_section": ([Section, _P, _P, _P], ctypes.c_int),
     "pentago_solve_sections": ([_P, ctypes.c_size_t, _P], ctypes.c_int),
-    "pentago_autotune_section": ([Section, _P, _P, _P, _P, _P], ctypes.c_int),
+    "pentago_autotune_section": ([Section, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "pentago_plan_create": ([_P, ctypes.c_size_t, _P], ctypes.c_int),
     "pentago_plan_launch": ([_P, _P], ctypes.c_int),
     "pentago_plan_launch_graph": ([_P, _P], ctypes.c_int),
@@ -205,13 +205,16 @@ def pentago_solve_section(counts, children, out, stream=None):
 
 def pentago_autotune_section(counts, children, out, stream=None):
     """Time the tile shapes of this section geometry, remember the fastest;
-    returns (tile lines, best ms).  out holds the sweep's result afterwards."""
+    returns (tile lines, workgroup size, best ms).  out holds the sweep's
+    result afterwards."""
     ch = (ctypes.c_void_p * 4)(*[None if c is None else c.data_ptr() for c in children])
     g = ctypes.c_int()
+    nt = ctypes.c_int()
     ms = ctypes.c_float()
     _check(lib().pentago_autotune_section(section(counts), ch, _dev_ptr(out), _stream(stream),
-                                          ctypes.byref(g), ctypes.byref(ms)), "pentago_autotune_section")
-    return g.value, ms.value
+                                          ctypes.byref(g), ctypes.byref(nt), ctypes.byref(ms)),
+           "pentago_autotune_section")
+    return g.value, nt.value, ms.value
 
 
 def _job_array(jobs):

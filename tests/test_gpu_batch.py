@@ -108,8 +108,8 @@ def test_autotuned_tiles_give_same_bytes(P):
     ch = solve(P, O.child_counts(counts, 3), [None] * 4)
     ref = solve(P, counts, [None, None, None, ch])
     out = torch.full_like(ref, -1)
-    g, ms = P.pentago_autotune_section(counts, [None, None, None, ch], out)
-    assert 1 <= g <= 8 and ms > 0
+    g, nt, ms = P.pentago_autotune_section(counts, [None, None, None, ch], out)
+    assert 1 <= g <= 8 and nt in (256, 512) and ms > 0
     assert torch.equal(ref, out)
     out2 = solve(P, counts, [None, None, None, ch])
     torch.cuda.synchronize()
