@@ -172,54 +172,62 @@ __device__ __forceinline__ uint2 cyl64(int p, uint32_t m)
     return make_uint2(lo, hi);
 }
 
-// LDS layout of one tile, per line: LineMasks of the 4 quadrants for both
-// colours, the 19 partial sets (18 chunk lines + U) for both colours, and the
-// 3 x 64 chunk tables for both colours.  Child records follow (18 dwords each:
-// A then B in the internal layout, 2 dwords of padding against bank clashes).
-constexpr int kLmqBytes = 2 * 4 * 12;
-constexpr int kOSlots = 22;                    // 18 chunk lines + U in 4 parts
-constexpr int kOBytes = 2 * kOSlots * 8;
+// LDS layout of one tile.  Per tile: the selectors of every position along D
+// for both colours, stored as [turn k][position] pairs (sel_c, sel_o) with a
+// row stride that puts the four turns of one position in different banks;
+// the children of every position; the selectors of the child positions.  Per
+// line: the chunk tables for both colours, the partial sets (18 chunk lines +
+// U) for both colours and the LineMasks of the 4 quadrants for both colours.
+// Child records (A then B in the internal layout, 2 dwords of padding) are
+// indexed [child position][line], so consecutive lanes of the child pass
+// write consecutive records.
+constexpr int kOSlots = 19;                    // 18 chunk lines + U
 constexpr int kLutStride = 2 * 3 * 64 + 1;    // uint2 per line; +1 staggers the banks of lines
-constexpr int kLutBytes = kLutStride * 8;
-constexpr int kLineBytes = kLmqBytes + kOBytes + kLutBytes;
 constexpr int kRecWords = 18;
 
-// Per position along D (shared by every line of the tile): the selectors of
-// the pattern for both colours and, for a parent position, its children as
-// (child index | k << 12) per empty cell.
-struct PosRec {
-    uint4 sel_c, sel_o;
-    uint16_t nchild, child[9];
-    uint32_t pad[3];
+struct PosChild {
+    uint16_t nchild, child[9];   // child index | k << 12 per empty cell
 };
 struct ChildPosRec {
     uint4 sel_c, sel_o;
 };
 
+__host__ __device__ __forceinline__ int sel_stride(int mD) { return ((mD + 15) & ~31) + 16; }
+
 struct TileLds {
-    LineMasks *lmq;   // [G][2][4]
-    uint2 *O;         // [G][2][kOSlots]
-    uint2 *lut;       // [G][kLutStride]
-    PosRec *pos;      // [mD]
     ChildPosRec *cpos;  // [cmD]
-    uint32_t *rec;    // [G][cmD][18]
+    uint2 *sel;         // [4][sel_stride(mD)]
+    uint2 *lut;         // [G][kLutStride]
+    uint2 *O;           // [G][2][kOSlots]
+    uint32_t *rec;      // [cmD][G][kRecWords]
+    LineMasks *lmq;     // [G][2][4]
+    PosChild *pch;      // [mD]
 };
+
+__host__ __device__ __forceinline__ int tile_lds_bytes(int G, int mD, int cmD, TileLds *L, char *base)
+{
+    int off = 0;
+    if (L) L->cpos = (ChildPosRec *)(base + off);
+    off += cmD * (int)sizeof(ChildPosRec);
+    if (L) L->sel = (uint2 *)(base + off);
+    off += 4 * sel_stride(mD) * 8;
+    if (L) L->lut = (uint2 *)(base + off);
+    off += G * kLutStride * 8;
+    if (L) L->O = (uint2 *)(base + off);
+    off += G * 2 * kOSlots * 8;
+    if (L) L->rec = (uint32_t *)(base + off);
+    off += cmD * G * kRecWords * 4;
+    if (L) L->lmq = (LineMasks *)(base + off);
+    off += G * 8 * (int)sizeof(LineMasks);
+    if (L) L->pch = (PosChild *)(base + off);
+    off += mD * (int)sizeof(PosChild);
+    return off;
+}
 
 __device__ __forceinline__ TileLds tile_lds(void *base, int G, int mD, int cmD)
 {
-    char *p = (char *)base;
     TileLds L;
-    L.pos = (PosRec *)p;
-    p += mD * sizeof(PosRec);
-    L.cpos = (ChildPosRec *)p;
-    p += cmD * sizeof(ChildPosRec);
-    L.lut = (uint2 *)p;
-    p += G * kLutBytes;
-    L.O = (uint2 *)p;
-    p += G * kOBytes;
-    L.lmq = (LineMasks *)p;
-    p += G * kLmqBytes;
-    L.rec = (uint32_t *)p;
+    tile_lds_bytes(G, mD, cmD, &L, (char *)base);
     return L;
 }
 
@@ -448,22 +456,24 @@ __global__ void __launch_bounds__(256)
 
 int sweep_lds_bytes(int G, int mD, int cmD)
 {
-    return (int)(mD * sizeof(PosRec) + cmD * sizeof(ChildPosRec)) + G * kLineBytes +
-           G * cmD * kRecWords * 4;
+    return tile_lds_bytes(G, mD, cmD, nullptr, nullptr);
 }
 
 template <int D>
 __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile, void *lds_base)
 {
+    // tile = ((i_O1 * m_O2) + i_O2) * ngroups + group of G lines along E
+    constexpr int E = D == 3 ? 2 : 3;
+    constexpr int O1 = D == 0 ? 1 : 0;
+    constexpr int O2 = D == 3 ? 1 : (D == 2 ? 1 : 2);
     const int grp = (int)(tile % J.ngroups);
     const long long rest = tile / J.ngroups;
-    const int mo2 = mdim(J, J.o2);
     Idx4 base;
-    base.v[0] = base.v[1] = base.v[2] = base.v[3] = 0;
-    set4(base, J.o2, (int)(rest % mo2));
-    set4(base, J.o1, (int)(rest / mo2));
-    set4(base, J.e, grp * J.G);
-    const int me = mdim(J, J.e);
+    base.v[D] = 0;
+    base.v[O2] = (int)(rest % J.m[O2]);
+    base.v[O1] = (int)(rest / J.m[O2]);
+    base.v[E] = grp * J.G;
+    const int me = J.m[E];
     const int nlines = min(J.G, me - grp * J.G);
     const int c = J.mover;
     const bool staged = (J.emask >> D) & 1;
@@ -484,7 +494,7 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
         const int it = threadIdx.x;
         const int ic = (int)(((uint32_t)it * rcp) >> 16);
         Idx4 idx = base;
-        set4(idx, J.e, get4(base, J.e) + (it - ic * nlines));
+        idx.v[E] = base.v[E] + (it - ic * nlines);
         idx.v[D] = ic;
         const uint4 *p = J.child[D] + 4 * block_offset(cshape, idx.v);
 #pragma unroll
@@ -492,27 +502,32 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
     }
 
     // Phase 0: per-line tables (LineMasks of the fixed quadrants, partial
-    // sets, chunk tables), for both colours.  Work items are kept small and
-    // even: 8 per line for the masks, 44 per line for the partial sets (the
-    // 15 lines that miss D are split in 4 parts), 24 per line for the tables.
+    // sets, chunk tables), for both colours, and the per-position records.
+    // Every work item is one small uniform task: a LineMasks, a position, one
+    // line's cylinder product, one chunk table entry.
     for (int it = threadIdx.x; it < nlines * 8; it += blockDim.x) {
         const int v = it >> 3, x = ((it >> 2) & 1) + 1, j = it & 3;
-        const int ij = get4(base, j) + (j == J.e ? v : 0);
+        const int ij = get4(base, j) + (j == E ? v : 0);
         const int qbj = j == 0 ? J.qb[0] : j == 1 ? J.qb[1] : j == 2 ? J.qb[2] : J.qb[3];
         const QInfo q = T.qinfo[j == D ? 0 : qbj + ij];
         const LineMasks lm = T.lm[j * 512 + (x == 1 ? q.bm : q.wm)];
         const bool keep = j != D;
         L.lmq[it] = LineMasks{keep ? lm.a : 0u, keep ? lm.b : 0u, keep ? lm.c : 0u};
+        if (j == 0) L.O[(2 * v + x - 1) * kOSlots + 18] = make_uint2(0, 0);  // U, ORed below
     }
     // positions along D, resolved once for all lines of the tile
     const int npos = mD + (staged ? cmD : 0);
+    const int sst = sel_stride(mD);
     for (int it = threadIdx.x; it < npos; it += blockDim.x) {
         if (it < mD) {
             const QInfo q = T.qinfo[J.qb[D] + it];
-            PosRec &r = L.pos[it];
             const unsigned mc = c == 1 ? q.bm : q.wm, mo = c == 1 ? q.wm : q.bm;
-            r.sel_c = T.sel[D * 512 + mc];
-            r.sel_o = T.sel[D * 512 + mo];
+            const uint4 sc = T.sel[D * 512 + mc], so = T.sel[D * 512 + mo];
+            L.sel[it] = make_uint2(sc.x, so.x);
+            L.sel[sst + it] = make_uint2(sc.y, so.y);
+            L.sel[2 * sst + it] = make_uint2(sc.z, so.z);
+            L.sel[3 * sst + it] = make_uint2(sc.w, so.w);
+            PosChild &r = L.pch[it];
             unsigned empt = staged ? ~(unsigned)(q.bm | q.wm) & 0x1ffu : 0u;
             int n = 0;
             while (empt) {
@@ -530,49 +545,38 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
         }
     }
     __syncthreads();
-    for (int it = threadIdx.x; it < nlines * 2 * kOSlots; it += blockDim.x) {
-        const int vx = it / kOSlots, slot = it % kOSlots;
+    // partial sets: item (line, colour, l) for the 18 chunk slots and the 15
+    // lines missing D (ORed into U); it / 33 by a 16-bit reciprocal, exact
+    // for it < 33 * 16
+    for (int it = threadIdx.x; it < nlines * 2 * 33; it += blockDim.x) {
+        const int vx = (int)(((uint32_t)it * 1986u) >> 16), l = it - 33 * vx;
         const LineMasks *lmq = L.lmq + 4 * vx;
-        uint2 r;
-        if (slot < 18) {
-            const uint32_t refs = T.chunk_ref[D * 18 + slot];
-            r = refs == 0xffffu ? make_uint2(0, 0) : ref_product<D>(lmq, refs, 2);
+        if (l < 18) {
+            const uint32_t refs = T.chunk_ref[D * 18 + l];
+            L.O[kOSlots * vx + l] = refs == 0xffffu ? make_uint2(0, 0) : ref_product<D>(lmq, refs, 2);
         } else {
-            r = make_uint2(0, 0);
-            for (int l = slot - 18; l < 15; l += 4) {
-                const uint2 p = ref_product<D>(lmq, T.u_ref[D * 15 + l], 3);
-                r.x |= p.x;
-                r.y |= p.y;
-            }
+            const uint2 p = ref_product<D>(lmq, T.u_ref[D * 15 + (l - 18)], 3);
+            uint32_t *u = (uint32_t *)(L.O + kOSlots * vx + 18);
+            if (p.x) atomicOr(u, p.x);
+            if (p.y) atomicOr(u + 1, p.y);
         }
-        L.O[it] = r;
     }
     __syncthreads();
-    // chunk tables: item (line, colour, chunk, quarter) writes 16 entries
-    for (int it = threadIdx.x; it < nlines * 2 * 3 * 4; it += blockDim.x) {
-        const int qq = it & 3, ch = (it >> 2) % 3, vx = it / 12;
+    // chunk tables: one entry per item, consecutive lanes on consecutive
+    // entries (line, colour, chunk, subset of the chunk's 6 lines)
+    for (int it = threadIdx.x; it < nlines * 2 * 3 * 64; it += blockDim.x) {
+        const int sigma = it & 63, g = it >> 6, vx = g / 3, ch = g - 3 * vx;
         const uint2 *O = L.O + kOSlots * vx + 6 * ch;
-        uint2 o[6];
+        uint2 r = ch == 0 ? L.O[kOSlots * vx + 18] : make_uint2(0, 0);
 #pragma unroll
-        for (int b = 0; b < 6; b++) o[b] = O[b];
-        uint2 base = make_uint2(0, 0);
-        if (ch == 0) {
-            const uint2 *U = L.O + kOSlots * vx + 18;
-            base.x = U[0].x | U[1].x | U[2].x | U[3].x;
-            base.y = U[0].y | U[1].y | U[2].y | U[3].y;
+        for (int b = 0; b < 6; b++) {
+            if ((sigma >> b) & 1) {
+                const uint2 o = O[b];
+                r.x |= o.x;
+                r.y |= o.y;
+            }
         }
-        if (qq & 1) { base.x |= o[4].x; base.y |= o[4].y; }
-        if (qq & 2) { base.x |= o[5].x; base.y |= o[5].y; }
-        uint2 *dst = L.lut + kLutStride * (vx >> 1) + 192 * (vx & 1) + 64 * ch + 16 * qq;
-#pragma unroll
-        for (int t = 0; t < 16; t++) {
-            uint2 r = base;
-            if (t & 1) { r.x |= o[0].x; r.y |= o[0].y; }
-            if (t & 2) { r.x |= o[1].x; r.y |= o[1].y; }
-            if (t & 4) { r.x |= o[2].x; r.y |= o[2].y; }
-            if (t & 8) { r.x |= o[3].x; r.y |= o[3].y; }
-            dst[t] = r;
-        }
+        L.lut[kLutStride * (vx >> 1) + 192 * (vx & 1) + 64 * ch + sigma] = r;
     }
     __syncthreads();
 
@@ -599,7 +603,7 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
             }
             Set256 A, B;
             child_terms(Fc, W, N, A, B);
-            uint32_t *r = L.rec + kRecWords * (v * cmD + ic);
+            uint32_t *r = L.rec + kRecWords * (ic * J.G + v);
 #pragma unroll
             for (int i = 0; i < 8; i += 2) {
                 *(uint2 *)(r + i) = make_uint2(A.w[i], A.w[i + 1]);
@@ -613,7 +617,7 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
             if (load_children) {
                 const int ic = (int)(((uint32_t)it * rcp) >> 16);
                 Idx4 idx = base;
-                set4(idx, J.e, get4(base, J.e) + (it - ic * nlines));
+                idx.v[E] = base.v[E] + (it - ic * nlines);
                 idx.v[D] = ic;
                 load_info(J.child[D] + 4 * block_offset(cshape, idx.v), W, N);
             } else {
@@ -627,70 +631,78 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
 
     // Phase 2: every parent entry of the tile (Fig. 3 "compute"), one quad
     // of lanes per parent, lane k computing word pair k (turn k of D in the
-    // internal layout).  Parents run along the memory order of a block: for
-    // D = 3 consecutive quads take consecutive positions along D (the
-    // fastest index), otherwise consecutive lines (dimension 3).
+    // internal layout).  Each quad walks one line; for D = 3 the quads of a
+    // line take consecutive positions along D (the fastest index of a block),
+    // otherwise consecutive quads take consecutive lines (dimension 3, the
+    // fastest index), so the quads of a wave store neighbouring entries.
     const int k = threadIdx.x & 3;
-    const int nparents = nlines * mD;
-    // pi / div as a multiply-high by ceil(2^32 / div): exact for pi < 2^32 / div
-    // (pi < 8 * 420 here); div = 1 has no 32-bit multiplier and is kept apart
-    const uint32_t div = D == 3 ? (uint32_t)mD : (uint32_t)nlines;
-    const uint32_t magic = div > 1 ? 0xffffffffu / div + 1u : 0u;
-    const int shape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
-    for (int it = threadIdx.x; it < 4 * ((nparents + 15) & ~15); it += blockDim.x) {
-        const int pi0 = it >> 2;
-        const bool ok = pi0 < nparents;
-        const int pi = ok ? pi0 : nparents - 1;  // a padding quad repeats the last parent
-        const int hiq = div > 1 ? (int)__umulhi((uint32_t)pi, magic) : pi;
-        const int loq = pi - hiq * (int)div;
-        const int v = D == 3 ? hiq : loq;
-        const int iD = D == 3 ? loq : hiq;
-        const PosRec &pr = L.pos[iD];
-        uint2 Wnt = make_uint2(0, 0);
-        uint2 Nnt = J.emask == 0 ? make_uint2(0xffffffffu, 0xffffffffu) : make_uint2(0, 0);
-        if (staged) {
-            const uint32_t *line = L.rec + kRecWords * (v * cmD);
-            const int n = pr.nchild;
-            for (int e = 0; e < n; e++) {
-                const uint16_t cc = pr.child[e];
-                const uint32_t *r = line + kRecWords * (cc & 0xfff) + 2 * ((k - (cc >> 12)) & 3);
-                const uint2 a = *(const uint2 *)r, b = *(const uint2 *)(r + 8);
-                Wnt.x |= a.x; Wnt.y |= a.y;
-                Nnt.x |= b.x; Nnt.y |= b.y;
-            }
-        }
+    const int nq = blockDim.x >> 2, qid = threadIdx.x >> 2;
+    int v, iD, step;
+    if (D == 3) {
+        const int qpl = nq / nlines;  // quads per line (nlines <= 8 <= nq)
+        v = qid / qpl;
+        iD = qid - v * qpl;
+        step = qpl;
+    } else {
+        const int per = nq / nlines;  // positions taken at once
+        v = qid % nlines;
+        iD = qid / nlines;
+        step = per;
+        if (iD >= per) v = nlines;  // spare quads
+    }
+    if (v < nlines) {
         Idx4 idx = base;
-        set4(idx, J.e, get4(base, J.e) + v);
-        idx.v[D] = iD;
-        // Children along the other dimensions with empty cells.
-        if (J.emask & ~(1 << D)) {
-            QInfo q[4];
-#pragma unroll
-            for (int j = 0; j < 4; j++) q[j] = T.qinfo[J.qb[j] + idx.v[j]];
-            if (D != 0 && (J.emask & 1)) direct_children_pair<D, 0>(J, T, idx, q[0], k, Wnt, Nnt);
-            if (D != 1 && (J.emask & 2)) direct_children_pair<D, 1>(J, T, idx, q[1], k, Wnt, Nnt);
-            if (D != 2 && (J.emask & 4)) direct_children_pair<D, 2>(J, T, idx, q[2], k, Wnt, Nnt);
-            if (D != 3 && (J.emask & 8)) direct_children_pair<D, 3>(J, T, idx, q[3], k, Wnt, Nnt);
-        }
+        idx.v[E] = base.v[E] + v;
         const uint2 *lut = L.lut + kLutStride * v;
-        const uint2 Fc = five_pair(lut + 192 * (c - 1), ((const uint32_t *)&pr.sel_c)[k]);
-        const uint2 Fo = five_pair(lut + 192 * (2 - c), ((const uint32_t *)&pr.sel_o)[k]);
-        uint2 W, N;
-        W.x = ~Fo.x & (Fc.x | Wnt.x);
-        W.y = ~Fo.y & (Fc.y | Wnt.y);
-        N.x = Fc.x | (~Fo.x & Nnt.x);
-        N.y = Fc.y | (~Fo.y & Nnt.y);
-        quad_swap_with3<D>(W, k);
-        quad_swap_with3<D>(N, k);
-        // lane j of the quad stores dwords 4j..4j+3 of the entry: W pairs
-        // (0,1), W pairs (2,3), N pairs (0,1), N pairs (2,3)
-        const uint32_t we0 = quad_perm<kQuadEven>(W.x), we1 = quad_perm<kQuadEven>(W.y);
-        const uint32_t wo0 = quad_perm<kQuadOdd>(W.x), wo1 = quad_perm<kQuadOdd>(W.y);
-        const uint32_t ne0 = quad_perm<kQuadEven>(N.x), ne1 = quad_perm<kQuadEven>(N.y);
-        const uint32_t no0 = quad_perm<kQuadOdd>(N.x), no1 = quad_perm<kQuadOdd>(N.y);
-        const bool isw = k < 2;
-        const uint4 piece = make_uint4(isw ? we0 : ne0, isw ? we1 : ne1, isw ? wo0 : no0, isw ? wo1 : no1);
-        if (ok) J.out[4 * block_offset(shape, idx.v) + k] = piece;
+        const uint2 *lutc = lut + 192 * (c - 1), *luto = lut + 192 * (2 - c);
+        const uint32_t *line = L.rec + kRecWords * v;
+        const int shape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
+        const uint2 nnt0 = J.emask == 0 ? make_uint2(0xffffffffu, 0xffffffffu) : make_uint2(0, 0);
+        for (; iD < mD; iD += step) {
+            idx.v[D] = iD;
+            const PosChild &pr = L.pch[iD];
+            const uint2 sel = L.sel[k * sst + iD];
+            uint2 Wnt = make_uint2(0, 0), Nnt = nnt0;
+            if (staged) {
+                const int n = pr.nchild;
+                for (int e = 0; e < n; e++) {
+                    const uint32_t cc = pr.child[e];
+                    // word pair k of the child's terms shifted by kc along D
+                    const uint32_t *r = line + kRecWords * J.G * (cc & 0xfff) + 2 * ((k - (cc >> 12)) & 3);
+                    const uint2 a = *(const uint2 *)r, b = *(const uint2 *)(r + 8);
+                    Wnt.x |= a.x; Wnt.y |= a.y;
+                    Nnt.x |= b.x; Nnt.y |= b.y;
+                }
+            }
+            // Children along the other dimensions with empty cells.
+            if (J.emask & ~(1 << D)) {
+                QInfo q[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) q[j] = T.qinfo[J.qb[j] + idx.v[j]];
+                if (D != 0 && (J.emask & 1)) direct_children_pair<D, 0>(J, T, idx, q[0], k, Wnt, Nnt);
+                if (D != 1 && (J.emask & 2)) direct_children_pair<D, 1>(J, T, idx, q[1], k, Wnt, Nnt);
+                if (D != 2 && (J.emask & 4)) direct_children_pair<D, 2>(J, T, idx, q[2], k, Wnt, Nnt);
+                if (D != 3 && (J.emask & 8)) direct_children_pair<D, 3>(J, T, idx, q[3], k, Wnt, Nnt);
+            }
+            const uint2 Fc = five_pair(lutc, sel.x);
+            const uint2 Fo = five_pair(luto, sel.y);
+            uint2 W, N;
+            W.x = ~Fo.x & (Fc.x | Wnt.x);
+            W.y = ~Fo.y & (Fc.y | Wnt.y);
+            N.x = Fc.x | (~Fo.x & Nnt.x);
+            N.y = Fc.y | (~Fo.y & Nnt.y);
+            quad_swap_with3<D>(W, k);
+            quad_swap_with3<D>(N, k);
+            // lane j of the quad stores dwords 4j..4j+3 of the entry: W pairs
+            // (0,1), W pairs (2,3), N pairs (0,1), N pairs (2,3)
+            const uint32_t we0 = quad_perm<kQuadEven>(W.x), we1 = quad_perm<kQuadEven>(W.y);
+            const uint32_t wo0 = quad_perm<kQuadOdd>(W.x), wo1 = quad_perm<kQuadOdd>(W.y);
+            const uint32_t ne0 = quad_perm<kQuadEven>(N.x), ne1 = quad_perm<kQuadEven>(N.y);
+            const uint32_t no0 = quad_perm<kQuadOdd>(N.x), no1 = quad_perm<kQuadOdd>(N.y);
+            const bool isw = k < 2;
+            J.out[4 * block_offset(shape, idx.v) + k] =
+                make_uint4(isw ? we0 : ne0, isw ? we1 : ne1, isw ? wo0 : no0, isw ? wo1 : no1);
+        }
     }
 }
 
