@@ -274,13 +274,24 @@ __device__ __forceinline__ Set256 five_lut(const uint2 *lut, const uint4 sel)
     return F;
 }
 
+// OR into acc the 8-word set at p shifted by k along internal dimension 3
+// (a re-addressing of the four word pairs).
+__device__ __forceinline__ void or_rotated(Set256 &acc, const uint32_t *p, int k)
+{
+#pragma unroll
+    for (int g3 = 0; g3 < 4; g3++) {
+        const uint2 v = *(const uint2 *)(p + 2 * ((g3 - k) & 3));
+        acc.w[2 * g3] |= v.x;
+        acc.w[2 * g3 + 1] |= v.y;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Quad form of the parent pass: the four lanes of a quad share one parent
-// entry, lane k owning word pair k (internal dimension 3 = turn k of the
-// staged quadrant D).  Every term of the recurrence is local to a word pair
-// except the exchange of dimensions D and 3, which becomes a data exchange
-// inside the quad (DPP quad permutations), and the final store, where the
-// quad writes the entry's 64 bytes as four contiguous 16-byte pieces.
+// Stores of the parent pass.  Each lane computes one parent entry (64 B, four
+// 16-byte pieces).  The four lanes of a quad then transpose their pieces in
+// registers (two exchange stages of DPP quad permutations), so that in each
+// of four store instructions the quad writes one whole entry and the 16 quads
+// of a wave write 16 neighbouring entries: full, contiguous 1 KB stores.
 // ---------------------------------------------------------------------------
 
 template <int CTRL>
@@ -288,85 +299,42 @@ __device__ __forceinline__ uint32_t quad_perm(uint32_t x)
 {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, true);
 }
-constexpr int kQuadXor1 = 0xB1;   // lanes [1,0,3,2]
-constexpr int kQuadXor2 = 0x4E;   // lanes [2,3,0,1]
-constexpr int kQuadEven = 0x88;   // lanes [0,2,0,2]
-constexpr int kQuadOdd = 0xDD;    // lanes [1,3,1,3]
 
-template <int LB>
-__device__ __forceinline__ uint32_t quad_partner(uint32_t x)
+// quad lanes [1,0,3,2] (X = 1) or [2,3,0,1] (X = 2)
+template <int X>
+__device__ __forceinline__ uint4 quad_xor(uint4 a)
 {
-    return LB == 0 ? quad_perm<kQuadXor1>(x) : quad_perm<kQuadXor2>(x);
+    constexpr int ctrl = X == 1 ? 0xB1 : 0x4E;
+    return make_uint4(quad_perm<ctrl>(a.x), quad_perm<ctrl>(a.y), quad_perm<ctrl>(a.z), quad_perm<ctrl>(a.w));
 }
 
-// Cross-lane swap_index_bits<I, LB + 1> on a set spread over a quad (lane k
-// holds words 2k and 2k+1, so word-index bit LB + 1 is lane bit LB).
-template <int I, int LB>
-__device__ __forceinline__ void quad_swap_bits(uint2 &x, int k)
+// One exchange stage: slot p of lane l takes slot p ^ X of lane l ^ X when
+// bit X of l differs from bit X of p.
+template <int X>
+__device__ __forceinline__ void quad_stage(uint4 (&r)[4], int l)
 {
-    constexpr int s = 1 << I;
-    constexpr uint32_t M = I == 0 ? 0x55555555u : I == 1 ? 0x33333333u : I == 2 ? 0x0f0f0f0fu
-                         : I == 3 ? 0x00ff00ffu : 0x0000ffffu;
-    const bool hi = (k >> LB) & 1;
-    const uint32_t px = quad_partner<LB>(x.x), py = quad_partner<LB>(x.y);
-    uint32_t lo = hi ? px : x.x, up = hi ? x.x : px;
-    uint32_t t = ((lo >> s) ^ up) & M;
-    x.x = hi ? (up ^ t) : (lo ^ (t << s));
-    lo = hi ? py : x.y;
-    up = hi ? x.y : py;
-    t = ((lo >> s) ^ up) & M;
-    x.y = hi ? (up ^ t) : (lo ^ (t << s));
-}
-
-// swap_with3<D> on a set spread over a quad (self-inverse, as swap_with3).
-template <int D>
-__device__ __forceinline__ void quad_swap_with3(uint2 &x, int k)
-{
-    if constexpr (D == 3) {
-        return;
-    } else if constexpr (D == 2) {
-        quad_swap_bits<4, 1 - 1>(x, k);
-        // words 1 <-> 4 and 3 <-> 6: word-in-pair bit <-> lane bit 1
-        const uint32_t px = quad_perm<kQuadXor2>(x.x), py = quad_perm<kQuadXor2>(x.y);
-        if ((k >> 1) & 1) x.x = py;
-        else x.y = px;
-    } else {
-        quad_swap_bits<2 * D, 0>(x, k);
-        quad_swap_bits<2 * D + 1, 1>(x, k);
-    }
-}
-
-// Word pair k of a five-set from the line's chunk tables (see five_lut).
-__device__ __forceinline__ uint2 five_pair(const uint2 *lut, uint32_t sel)
-{
-    const char *base = (const char *)lut;
-    const uint2 a = *(const uint2 *)(base + (sel & 1023u));
-    const uint2 b = *(const uint2 *)(base + ((sel >> 10) & 1023u));
-    const uint2 c = *(const uint2 *)(base + (sel >> 20));
-    return make_uint2(a.x | b.x | c.x, a.y | b.y | c.y);
-}
-
-// shift_dim restricted to one word pair, for dimensions 0..2 (which never
-// move bits between word pairs).
-__device__ __forceinline__ uint2 shift_pair(uint2 x, int d, int k)
-{
-    Set256 t;
-    t.w[0] = x.x;
-    t.w[1] = x.y;
+    uint4 t[4];
 #pragma unroll
-    for (int i = 2; i < 8; i++) t.w[i] = 0;
-    const Set256 r = shift_dim(t, d, k);
-    return make_uint2(r.w[0], r.w[1]);
+    for (int p = 0; p < 4; p++) t[p] = quad_xor<X>(r[p ^ X]);
+#pragma unroll
+    for (int p = 0; p < 4; p++)
+        if ((l ^ p) & X) r[p] = t[p];
+}
+
+// After this, slot p of quad lane l holds piece l of quad lane p's entry.
+__device__ __forceinline__ void quad_transpose(uint4 (&r)[4], int l)
+{
+    quad_stage<2>(r, l);
+    quad_stage<1>(r, l);
 }
 
 // Children of one parent along a dimension JD that is not staged: their
 // A/B terms were prepared per child entry by prep_kernel, in the parent's
 // internal layout (64 B each, in the child section's blocked order).
-// In the quad parent pass lane k reads word pair k of each prepared term.
 template <int D, int JD>
-__device__ __forceinline__ void direct_children_pair(const SweepJob &J, const DevTables &T,
-                                                     const Idx4 &idx, const QInfo &q, int k,
-                                                     uint2 &Wnt, uint2 &Nnt)
+__device__ __forceinline__ void direct_children(const SweepJob &J, const DevTables &T,
+                                                const Idx4 &idx, const QInfo &q, Set256 &Wnt,
+                                                Set256 &Nnt)
 {
     int cshape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
     cshape[JD] = J.cm[JD];
@@ -378,11 +346,9 @@ __device__ __forceinline__ void direct_children_pair(const SweepJob &J, const De
         const uint16_t cc = T.canon[q.code + J.mover * c_pow3[cell]];
         Idx4 cidx = idx;
         cidx.v[JD] = cc & 0xfff;
-        const uint2 *p = (const uint2 *)(J.prep[JD] + 4 * block_offset(cshape, cidx.v));
-        const uint2 a = shift_pair(p[k], ip, cc >> 12);
-        const uint2 b = shift_pair(p[4 + k], ip, cc >> 12);
-        Wnt.x |= a.x; Wnt.y |= a.y;
-        Nnt.x |= b.x; Nnt.y |= b.y;
+        const uint4 *p = J.prep[JD] + 4 * block_offset(cshape, cidx.v);
+        s_or_into(Wnt, shift_dim(set_from(p), ip, cc >> 12));
+        s_or_into(Nnt, shift_dim(set_from(p + 2), ip, cc >> 12));
     }
 }
 
@@ -562,21 +528,25 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
         }
     }
     __syncthreads();
-    // chunk tables: one entry per item, consecutive lanes on consecutive
-    // entries (line, colour, chunk, subset of the chunk's 6 lines)
-    for (int it = threadIdx.x; it < nlines * 2 * 3 * 64; it += blockDim.x) {
-        const int sigma = it & 63, g = it >> 6, vx = g / 3, ch = g - 3 * vx;
+    // chunk tables: item (line, colour, chunk, subset s of the chunk's first
+    // 5 lines) writes entries s and s + 32 (the 6th line added); 32
+    // consecutive lanes write 32 consecutive entries
+    for (int it = threadIdx.x; it < nlines * 2 * 3 * 32; it += blockDim.x) {
+        const int sigma = it & 31, g = it >> 5, vx = g / 3, ch = g - 3 * vx;
         const uint2 *O = L.O + kOSlots * vx + 6 * ch;
         uint2 r = ch == 0 ? L.O[kOSlots * vx + 18] : make_uint2(0, 0);
 #pragma unroll
-        for (int b = 0; b < 6; b++) {
+        for (int b = 0; b < 5; b++) {
             if ((sigma >> b) & 1) {
                 const uint2 o = O[b];
                 r.x |= o.x;
                 r.y |= o.y;
             }
         }
-        L.lut[kLutStride * (vx >> 1) + 192 * (vx & 1) + 64 * ch + sigma] = r;
+        uint2 *dst = L.lut + kLutStride * (vx >> 1) + 192 * (vx & 1) + 64 * ch + sigma;
+        const uint2 o5 = O[5];
+        dst[0] = r;
+        dst[32] = make_uint2(r.x | o5.x, r.y | o5.y);
     }
     __syncthreads();
 
@@ -629,80 +599,67 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
         __syncthreads();
     }
 
-    // Phase 2: every parent entry of the tile (Fig. 3 "compute"), one quad
-    // of lanes per parent, lane k computing word pair k (turn k of D in the
-    // internal layout).  Each quad walks one line; for D = 3 the quads of a
-    // line take consecutive positions along D (the fastest index of a block),
-    // otherwise consecutive quads take consecutive lines (dimension 3, the
-    // fastest index), so the quads of a wave store neighbouring entries.
-    const int k = threadIdx.x & 3;
-    const int nq = blockDim.x >> 2, qid = threadIdx.x >> 2;
-    int v, iD, step;
-    if (D == 3) {
-        const int qpl = nq / nlines;  // quads per line (nlines <= 8 <= nq)
-        v = qid / qpl;
-        iD = qid - v * qpl;
-        step = qpl;
-    } else {
-        const int per = nq / nlines;  // positions taken at once
-        v = qid % nlines;
-        iD = qid / nlines;
-        step = per;
-        if (iD >= per) v = nlines;  // spare quads
-    }
-    if (v < nlines) {
+    // Phase 2: every parent entry of the tile (Fig. 3 "compute").  A wave
+    // takes 64 parents that are consecutive in memory order (for D = 3 along
+    // D, the fastest index of a block; otherwise along the lines, dimension
+    // 3); quad lane l of quad q computes parent 16 l + q, so after the quad
+    // transpose store p writes parents 16 p .. 16 p + 15.
+    const int lane = threadIdx.x & 63, l4 = lane & 3, q = lane >> 2;
+    const int nwaves = blockDim.x >> 6;
+    const int nparents = nlines * mD;
+    // P / div as a multiply-high by ceil(2^32 / div): exact for P < 2^32 / div
+    // (P < 8 * 420 here); div = 1 has no 32-bit multiplier and is kept apart
+    const uint32_t div = D == 3 ? (uint32_t)mD : (uint32_t)nlines;
+    const uint32_t magic = div > 1 ? 0xffffffffu / div + 1u : 0u;
+    const int shape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
+    for (int g0 = (threadIdx.x >> 6) * 64; g0 < nparents; g0 += nwaves * 64) {
+        const int P = min(g0 + 16 * l4 + q, nparents - 1);  // a spare lane repeats the last parent
+        const int hiq = div > 1 ? (int)__umulhi((uint32_t)P, magic) : P;
+        const int loq = P - hiq * (int)div;
+        const int v = D == 3 ? hiq : loq;
+        const int iD = D == 3 ? loq : hiq;
         Idx4 idx = base;
         idx.v[E] = base.v[E] + v;
-        const uint2 *lut = L.lut + kLutStride * v;
-        const uint2 *lutc = lut + 192 * (c - 1), *luto = lut + 192 * (2 - c);
-        const uint32_t *line = L.rec + kRecWords * v;
-        const int shape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
-        const uint2 nnt0 = J.emask == 0 ? make_uint2(0xffffffffu, 0xffffffffu) : make_uint2(0, 0);
-        for (; iD < mD; iD += step) {
-            idx.v[D] = iD;
+        idx.v[D] = iD;
+        Set256 Wnt = s_zero(), Nnt = J.emask == 0 ? s_full() : s_zero();
+        if (staged) {
             const PosChild &pr = L.pch[iD];
-            const uint2 sel = L.sel[k * sst + iD];
-            uint2 Wnt = make_uint2(0, 0), Nnt = nnt0;
-            if (staged) {
-                const int n = pr.nchild;
-                for (int e = 0; e < n; e++) {
-                    const uint32_t cc = pr.child[e];
-                    // word pair k of the child's terms shifted by kc along D
-                    const uint32_t *r = line + kRecWords * J.G * (cc & 0xfff) + 2 * ((k - (cc >> 12)) & 3);
-                    const uint2 a = *(const uint2 *)r, b = *(const uint2 *)(r + 8);
-                    Wnt.x |= a.x; Wnt.y |= a.y;
-                    Nnt.x |= b.x; Nnt.y |= b.y;
-                }
+            const uint32_t *line = L.rec + kRecWords * v;
+            const int n = pr.nchild;
+            for (int e = 0; e < n; e++) {
+                const uint32_t cc = pr.child[e];
+                const uint32_t *r = line + kRecWords * J.G * (cc & 0xfff);
+                or_rotated(Wnt, r, cc >> 12);
+                or_rotated(Nnt, r + 8, cc >> 12);
             }
-            // Children along the other dimensions with empty cells.
-            if (J.emask & ~(1 << D)) {
-                QInfo q[4];
-#pragma unroll
-                for (int j = 0; j < 4; j++) q[j] = T.qinfo[J.qb[j] + idx.v[j]];
-                if (D != 0 && (J.emask & 1)) direct_children_pair<D, 0>(J, T, idx, q[0], k, Wnt, Nnt);
-                if (D != 1 && (J.emask & 2)) direct_children_pair<D, 1>(J, T, idx, q[1], k, Wnt, Nnt);
-                if (D != 2 && (J.emask & 4)) direct_children_pair<D, 2>(J, T, idx, q[2], k, Wnt, Nnt);
-                if (D != 3 && (J.emask & 8)) direct_children_pair<D, 3>(J, T, idx, q[3], k, Wnt, Nnt);
-            }
-            const uint2 Fc = five_pair(lutc, sel.x);
-            const uint2 Fo = five_pair(luto, sel.y);
-            uint2 W, N;
-            W.x = ~Fo.x & (Fc.x | Wnt.x);
-            W.y = ~Fo.y & (Fc.y | Wnt.y);
-            N.x = Fc.x | (~Fo.x & Nnt.x);
-            N.y = Fc.y | (~Fo.y & Nnt.y);
-            quad_swap_with3<D>(W, k);
-            quad_swap_with3<D>(N, k);
-            // lane j of the quad stores dwords 4j..4j+3 of the entry: W pairs
-            // (0,1), W pairs (2,3), N pairs (0,1), N pairs (2,3)
-            const uint32_t we0 = quad_perm<kQuadEven>(W.x), we1 = quad_perm<kQuadEven>(W.y);
-            const uint32_t wo0 = quad_perm<kQuadOdd>(W.x), wo1 = quad_perm<kQuadOdd>(W.y);
-            const uint32_t ne0 = quad_perm<kQuadEven>(N.x), ne1 = quad_perm<kQuadEven>(N.y);
-            const uint32_t no0 = quad_perm<kQuadOdd>(N.x), no1 = quad_perm<kQuadOdd>(N.y);
-            const bool isw = k < 2;
-            J.out[4 * block_offset(shape, idx.v) + k] =
-                make_uint4(isw ? we0 : ne0, isw ? we1 : ne1, isw ? wo0 : no0, isw ? wo1 : no1);
         }
+        // Children along the other dimensions with empty cells.
+        if (J.emask & ~(1 << D)) {
+            QInfo qi[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) qi[j] = T.qinfo[J.qb[j] + idx.v[j]];
+            if (D != 0 && (J.emask & 1)) direct_children<D, 0>(J, T, idx, qi[0], Wnt, Nnt);
+            if (D != 1 && (J.emask & 2)) direct_children<D, 1>(J, T, idx, qi[1], Wnt, Nnt);
+            if (D != 2 && (J.emask & 4)) direct_children<D, 2>(J, T, idx, qi[2], Wnt, Nnt);
+            if (D != 3 && (J.emask & 8)) direct_children<D, 3>(J, T, idx, qi[3], Wnt, Nnt);
+        }
+        const uint2 *lut = L.lut + kLutStride * v;
+        const uint2 s0 = L.sel[iD], s1 = L.sel[sst + iD], s2 = L.sel[2 * sst + iD], s3 = L.sel[3 * sst + iD];
+        const Set256 Fc = five_lut(lut + 192 * (c - 1), make_uint4(s0.x, s1.x, s2.x, s3.x));
+        const Set256 Fo = five_lut(lut + 192 * (2 - c), make_uint4(s0.y, s1.y, s2.y, s3.y));
+        Set256 W, N;
+        combine(Fc, Fo, Wnt, Nnt, W, N);
+        swap_with3<D>(W);
+        swap_with3<D>(N);
+        uint4 r[4] = {make_uint4(W.w[0], W.w[1], W.w[2], W.w[3]), make_uint4(W.w[4], W.w[5], W.w[6], W.w[7]),
+                      make_uint4(N.w[0], N.w[1], N.w[2], N.w[3]), make_uint4(N.w[4], N.w[5], N.w[6], N.w[7])};
+        quad_transpose(r, l4);
+        const uint32_t off = block_offset(shape, idx.v);
+        const uint32_t offs[4] = {quad_perm<0x00>(off), quad_perm<0x55>(off), quad_perm<0xAA>(off),
+                                  quad_perm<0xFF>(off)};
+#pragma unroll
+        for (int p = 0; p < 4; p++)
+            if (g0 + 16 * p + q < nparents) J.out[4 * offs[p] + l4] = r[p];
     }
 }
 
