@@ -153,25 +153,6 @@ __device__ __forceinline__ Set256 set_from(const uint4 *p)
 // only on D's pattern and come from T.sel.
 // ---------------------------------------------------------------------------
 
-// Cylinder over internal dimensions 0..2 (bit a0 + 4 a1 + 16 a2 of a word
-// pair): the elements whose coordinate p lies in the 4-bit set m.
-__device__ __forceinline__ uint2 cyl64(int p, uint32_t m)
-{
-    if (p == 0) {
-        uint32_t h = m * 0x1111u;
-        h |= h << 16;
-        return make_uint2(h, h);
-    }
-    if (p == 1) {
-        uint32_t h = fill_g1(m);
-        h |= h << 16;
-        return make_uint2(h, h);
-    }
-    const uint32_t lo = ((m & 1u) ? 0x0000ffffu : 0u) | ((m & 2u) ? 0xffff0000u : 0u);
-    const uint32_t hi = ((m & 4u) ? 0x0000ffffu : 0u) | ((m & 8u) ? 0xffff0000u : 0u);
-    return make_uint2(lo, hi);
-}
-
 // LDS layout of one tile.  Per tile: the selectors of every position along D
 // for both colours, stored as [turn k][position] pairs (sel_c, sel_o) with a
 // row stride that puts the four turns of one position in different banks;
@@ -231,29 +212,37 @@ __device__ __forceinline__ TileLds tile_lds(void *base, int G, int mD, int cmD)
     return L;
 }
 
-__device__ __forceinline__ uint32_t ref_mu(const LineMasks *lmq, uint32_t ref)
+// A line reference: quadrant j (bits 0-1), LineMasks field f (bits 2-3) and
+// nibble i (bits 4-7); 0xff stands for no quadrant.  ref_cyl gives the
+// cylinder over the internal dimension of quadrant j of the turns after
+// which the line's cells in quadrant j hold the colour (all of L for 0xff).
+// Branch-free, as the lanes of a wave carry different references.
+template <int D>
+__device__ __forceinline__ uint2 ref_cyl(const LineMasks *lmq, uint32_t ref)
 {
-    const LineMasks L = lmq[ref & 3];
-    const uint32_t f = (ref >> 2) & 3;
-    const uint32_t fld = f == 0 ? L.a : f == 1 ? L.b : L.c;
-    return (fld >> (4 * (ref >> 4))) & 0xfu;
+    const bool none = ref == 0xffu;
+    const uint32_t j = ref & 3, f = (ref >> 2) & 3;
+    const uint32_t fld = ((const uint32_t *)(lmq + j))[none ? 0 : f];
+    const uint32_t m = none ? 0xfu : (fld >> (4 * (ref >> 4))) & 0xfu;
+    // internal position of quadrant j when D is exchanged with 3
+    const uint32_t p = j == 3 ? (uint32_t)D : j;
+    const uint32_t c0 = m * 0x1111u;          // p = 0: a set of g0, every g1
+    const uint32_t c1 = spread1(m) * 0xfu;    // p = 1: a set of g1, every g0
+    const uint32_t h = p == 0 ? c0 : c1;
+    const uint32_t lo = ((m & 1u) ? 0x0000ffffu : 0u) | ((m & 2u) ? 0xffff0000u : 0u);
+    const uint32_t hi = ((m & 4u) ? 0x0000ffffu : 0u) | ((m & 8u) ? 0xffff0000u : 0u);
+    const uint32_t hh = h | (h << 16);
+    return p == 2 && !none ? make_uint2(lo, hi) : make_uint2(hh, hh);
 }
 
-// internal position of quadrant j when D is exchanged with 3 (j != D)
-__device__ __forceinline__ int ipos(int j, int D) { return j == 3 ? D : j; }
-
+// Product of the cylinders of up to three references (refs: one per byte).
 template <int D>
-__device__ __forceinline__ uint2 ref_product(const LineMasks *lmq, uint32_t refs, int nref)
+__device__ __forceinline__ uint2 ref_product3(const LineMasks *lmq, uint32_t refs)
 {
-    uint2 r = make_uint2(0xffffffffu, 0xffffffffu);
-    for (int i = 0; i < nref; i++) {
-        const uint32_t ref = (refs >> (8 * i)) & 0xffu;
-        if (ref == 0xffu) break;
-        const uint2 c = cyl64(ipos(ref & 3, D), ref_mu(lmq, ref));
-        r.x &= c.x;
-        r.y &= c.y;
-    }
-    return r;
+    const uint2 a = ref_cyl<D>(lmq, refs & 0xffu);
+    const uint2 b = ref_cyl<D>(lmq, (refs >> 8) & 0xffu);
+    const uint2 c = ref_cyl<D>(lmq, (refs >> 16) & 0xffu);
+    return make_uint2(a.x & b.x & c.x, a.y & b.y & c.y);
 }
 
 // Five-set of a board of the line from the line's chunk tables and the
@@ -517,14 +506,17 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
     for (int it = threadIdx.x; it < nlines * 2 * 33; it += blockDim.x) {
         const int vx = (int)(((uint32_t)it * 1986u) >> 16), l = it - 33 * vx;
         const LineMasks *lmq = L.lmq + 4 * vx;
+        // chunk slots carry two references (0xffff: unused slot), the lines
+        // missing D three
+        const uint32_t refs = l < 18 ? (uint32_t)T.chunk_ref[D * 18 + l] | 0xff0000u : T.u_ref[D * 15 + (l - 18)];
+        uint2 pr = ref_product3<D>(lmq, refs);
         if (l < 18) {
-            const uint32_t refs = T.chunk_ref[D * 18 + l];
-            L.O[kOSlots * vx + l] = refs == 0xffffu ? make_uint2(0, 0) : ref_product<D>(lmq, refs, 2);
+            if ((refs & 0xffffu) == 0xffffu) pr = make_uint2(0, 0);
+            L.O[kOSlots * vx + l] = pr;
         } else {
-            const uint2 p = ref_product<D>(lmq, T.u_ref[D * 15 + (l - 18)], 3);
             uint32_t *u = (uint32_t *)(L.O + kOSlots * vx + 18);
-            if (p.x) atomicOr(u, p.x);
-            if (p.y) atomicOr(u + 1, p.y);
+            if (pr.x) atomicOr(u, pr.x);
+            if (pr.y) atomicOr(u + 1, pr.y);
         }
     }
     __syncthreads();

@@ -58,36 +58,45 @@ PG_HD uint32_t bfi(uint32_t m, uint32_t a, uint32_t b) { return (m & a) | (~m & 
 // swap the two bytes of each 16-bit half
 PG_HD uint32_t swap_bytes16(uint32_t x) { return ((x >> 8) & 0x00ff00ffu) | ((x << 8) & 0xff00ff00u); }
 
-// rmax(X)(g) = OR over the 8 single-quadrant turns r of X(g + r) (Section III).
-// Along each dimension the two neighbours g_j +- 1 of g_j are the two values
-// of the other parity, so each dimension costs a pair-swap plus an OR:
-// OR in the element two steps away, then exchange the two parities.
-PG_HD Set256 rmax(const Set256 &x)
+// rmin(X)(g) = AND over the 8 single-quadrant turns r of X(g + r), so that
+// rmax(X) = not rmin(not X) (Section III's rmax, by De Morgan).  Along each
+// dimension the two neighbours g_j +- 1 of g_j are exactly the two values of
+// the other parity, so each dimension is "AND the two values of one parity,
+// then hand the result to the other parity":
+//   dimension 0 (bit pairs inside nibbles), dimension 1 (nibbles inside
+//   16-bit halves), dimension 2 (halves and the two words of a pair),
+//   dimension 3 (word pairs).
+PG_HD Set256 rmin(const Set256 &x)
 {
     Set256 r;
-    uint32_t n2[4];
+    uint32_t m2[4];
 #pragma unroll
-    for (int g3 = 0; g3 < 4; g3++) n2[g3] = rotr32(x.w[2 * g3] | x.w[2 * g3 + 1], 16);
-    uint32_t n3[4];
+    for (int g3 = 0; g3 < 4; g3++) m2[g3] = rotr32(x.w[2 * g3] & x.w[2 * g3 + 1], 16);
+    uint32_t m3[4];
 #pragma unroll
     for (int p = 0; p < 2; p++) {
-        n3[p] = x.w[2 + p] | x.w[6 + p];      // neighbours of g3 = 0 and 2
-        n3[2 + p] = x.w[0 + p] | x.w[4 + p];  // neighbours of g3 = 1 and 3
+        m3[p] = x.w[2 + p] & x.w[6 + p];      // neighbours of g3 = 0 and 2
+        m3[2 + p] = x.w[0 + p] & x.w[4 + p];  // neighbours of g3 = 1 and 3
     }
 #pragma unroll
     for (int w = 0; w < 8; w++) {
         const int g3 = w >> 1, p = w & 1;
         const uint32_t u = x.w[w];
-        // dimension 0: bits inside nibbles
-        const uint32_t y0 = ((u >> 2) & 0x33333333u) | ((u << 2) & 0xccccccccu) | u;
-        const uint32_t n0 = ((y0 >> 1) & 0x55555555u) | ((y0 << 1) & 0xaaaaaaaau);
-        // dimension 1: nibbles inside halves (a byte swap inside each half)
-        const uint32_t y1 = swap_bytes16(u) | u;
-        const uint32_t n1 = ((y1 >> 4) & 0x0f0f0f0fu) | ((y1 << 4) & 0xf0f0f0f0u);
-        r.w[w] = (n0 | n1) | (n2[g3] | n3[(g3 & 1) * 2 + p]);
+        // dimension 0: P holds (u0 & u2, u1 & u3) in bits 0, 1 of each nibble
+        const uint32_t P = u & (u >> 2) & 0x33333333u;
+        const uint32_t Q = ((P >> 1) & 0x11111111u) | ((P << 1) & 0x22222222u);
+        const uint32_t n0 = Q | (Q << 2);
+        // dimension 1: the same one level up, nibbles inside each half
+        const uint32_t P1 = u & (u >> 8) & 0x00ff00ffu;
+        const uint32_t Q1 = ((P1 >> 4) & 0x000f000fu) | ((P1 << 4) & 0x00f000f0u);
+        const uint32_t n1 = Q1 | (Q1 << 8);
+        r.w[w] = (n0 & n1) & (m2[g3] & m3[(g3 & 1) * 2 + p]);
     }
     return r;
 }
+
+// rmax(X)(g) = OR over the 8 single-quadrant turns r of X(g + r) (Section III).
+PG_HD Set256 rmax(const Set256 &x) { return s_not(rmin(s_not(x))); }
 
 // out(g) = in(g - k e_d): the table of a board whose quadrant d was turned k
 // more times (Section III, transform f_b -> f_{gb} with g = k e_d).
@@ -308,12 +317,13 @@ PG_HD void combine(const Set256 &Fc, const Set256 &Fo, const Set256 &Wnt, const 
 PG_HD void child_terms(const Set256 &Fparent_t, const Set256 &Wt, const Set256 &Nt, Set256 &A,
                        Set256 &B)
 {
-    Set256 a = rmax(s_not(Nt));
-    Set256 b = rmax(s_not(Wt));
+    // rmax(not X) = not rmin(X)
+    const Set256 a = rmin(Nt);
+    const Set256 b = rmin(Wt);
 #pragma unroll
     for (int i = 0; i < 8; i++) {
-        A.w[i] = Fparent_t.w[i] | a.w[i];
-        B.w[i] = Fparent_t.w[i] | b.w[i];
+        A.w[i] = Fparent_t.w[i] | ~a.w[i];
+        B.w[i] = Fparent_t.w[i] | ~b.w[i];
     }
 }
 
