@@ -421,12 +421,14 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
     constexpr int E = D == 3 ? 2 : 3;
     constexpr int O1 = D == 0 ? 1 : 0;
     constexpr int O2 = D == 3 ? 1 : (D == 2 ? 1 : 2);
-    const int grp = (int)(tile % J.ngroups);
-    const long long rest = tile / J.ngroups;
+    // (32-bit: a section has fewer than 2^32 entries, so fewer tiles)
+    const uint32_t t32 = (uint32_t)tile, ng = (uint32_t)J.ngroups, mo2 = (uint32_t)J.m[O2];
+    const uint32_t rest = t32 / ng;
+    const int grp = (int)(t32 - rest * ng);
     Idx4 base;
     base.v[D] = 0;
-    base.v[O2] = (int)(rest % J.m[O2]);
-    base.v[O1] = (int)(rest / J.m[O2]);
+    base.v[O1] = (int)(rest / mo2);
+    base.v[O2] = (int)(rest - (uint32_t)base.v[O1] * mo2);
     base.v[E] = grp * J.G;
     const int me = J.m[E];
     const int nlines = min(J.G, me - grp * J.G);
