@@ -36,6 +36,42 @@ __device__ __forceinline__ uint32_t block_offset(const int *m, const int *idx)
     return off;
 }
 
+// block_offset along a line of dimension D: with every index but idx[D]
+// fixed, the offset is c0 + c1 * B + c2 * s + c3 * r for B = idx[D] >> 3,
+// r = idx[D] & 7 and s = min(8, m[D] - 8 B) (the extent of that block).
+template <int D>
+__device__ __forceinline__ uint4 line_offset_coeffs(const int *m, const int *idx)
+{
+    uint32_t B[4], r[4], s[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        B[j] = (uint32_t)idx[j] >> 3;
+        r[j] = (uint32_t)idx[j] & 7u;
+        s[j] = min(8u, (uint32_t)m[j] - 8u * B[j]);
+    }
+    uint32_t c0 = 0, c1 = 8, c2 = 0, c3 = 1;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        uint32_t lo = 1, lo_d = 1, hi_m = 1, hi_s = 1, hi_s_d = 1;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            if (i < j) { lo *= s[i]; if (i != D) lo_d *= s[i]; }
+            if (i > j) { hi_m *= (uint32_t)m[i]; hi_s *= s[i]; if (i != D) hi_s_d *= s[i]; }
+        }
+        if (j < D) {
+            c0 += lo * 8u * B[j] * hi_m;   // whole blocks before, in dimensions < D
+            c2 += r[j] * hi_s_d;           // in-block index terms that carry s_D
+        } else if (j == D) {
+            c1 = lo * 8u * hi_m;
+            c3 = hi_s;
+        } else {
+            c2 += lo_d * 8u * B[j] * hi_m;  // whole blocks in dimensions > D carry s_D
+            c0 += r[j] * hi_s;
+        }
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
 __device__ __forceinline__ void load_info(const uint4 *p, Set256 &W, Set256 &N)
 {
     const uint4 a = p[0], b = p[1], c = p[2], d = p[3];
@@ -182,6 +218,7 @@ struct TileLds {
     uint2 *O;           // [G][2][kOSlots]
     uint32_t *rec;      // [cmD][G][kRecWords]
     LineMasks *lmq;     // [G][2][4]
+    uint4 *loff;        // [G] line_offset_coeffs of each line
     PosChild *pch;      // [mD]
 };
 
@@ -200,6 +237,8 @@ __host__ __device__ __forceinline__ int tile_lds_bytes(int G, int mD, int cmD, T
     off += cmD * G * kRecWords * 4;
     if (L) L->lmq = (LineMasks *)(base + off);
     off += G * 8 * (int)sizeof(LineMasks);
+    if (L) L->loff = (uint4 *)(base + off);
+    off += G * 16;
     if (L) L->pch = (PosChild *)(base + off);
     off += mD * (int)sizeof(PosChild);
     return off;
@@ -470,6 +509,11 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
         const LineMasks lm = T.lm[j * 512 + (x == 1 ? q.bm : q.wm)];
         const bool keep = j != D;
         L.lmq[it] = LineMasks{keep ? lm.a : 0u, keep ? lm.b : 0u, keep ? lm.c : 0u};
+        if ((it & 7) == 0) {
+            Idx4 li = base;
+            li.v[E] = base.v[E] + v;
+            L.loff[v] = line_offset_coeffs<D>(J.m, li.v);
+        }
         if (j == 0) L.O[(2 * v + x - 1) * kOSlots + 18] = make_uint2(0, 0);  // U, ORed below
     }
     // positions along D, resolved once for all lines of the tile
@@ -605,7 +649,6 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
     // (P < 8 * 420 here); div = 1 has no 32-bit multiplier and is kept apart
     const uint32_t div = D == 3 ? (uint32_t)mD : (uint32_t)nlines;
     const uint32_t magic = div > 1 ? 0xffffffffu / div + 1u : 0u;
-    const int shape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
     for (int g0 = (threadIdx.x >> 6) * 64; g0 < nparents; g0 += nwaves * 64) {
         const int P = min(g0 + 16 * l4 + q, nparents - 1);  // a spare lane repeats the last parent
         const int hiq = div > 1 ? (int)__umulhi((uint32_t)P, magic) : P;
@@ -648,7 +691,13 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
         uint4 r[4] = {make_uint4(W.w[0], W.w[1], W.w[2], W.w[3]), make_uint4(W.w[4], W.w[5], W.w[6], W.w[7]),
                       make_uint4(N.w[0], N.w[1], N.w[2], N.w[3]), make_uint4(N.w[4], N.w[5], N.w[6], N.w[7])};
         quad_transpose(r, l4);
-        const uint32_t off = block_offset(shape, idx.v);
+        const uint4 lc = L.loff[v];
+        const uint32_t bD = (uint32_t)iD >> 3;
+        const uint32_t sD = min(8u, (uint32_t)mD - 8u * bD), rD = (uint32_t)iD & 7u;
+        // for D = 3 every coefficient but c0 is below 2^13 (products of block
+        // extents), so 24-bit multiplies are exact
+        const uint32_t off = D == 3 ? lc.x + __umul24(lc.y, bD) + __umul24(lc.z, sD) + rD
+                                    : lc.x + lc.y * bD + lc.z * sD + lc.w * rD;
         const uint32_t offs[4] = {quad_perm<0x00>(off), quad_perm<0x55>(off), quad_perm<0xAA>(off),
                                   quad_perm<0xFF>(off)};
 #pragma unroll
