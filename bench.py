@@ -57,6 +57,29 @@ def cpu_baseline(entries, positions, seconds_target=15.0):
                       "retrograde on concrete boards, %d threads, %.1f s" % (n, n * pos_per_entry, threads, dt)}
 
 
+def _blob_sha(path):
+    """git's blob hash of a file (identifies the kernel source a profile was taken on)."""
+    import hashlib
+    with open(path, "rb") as f:
+        data = f.read()
+    return hashlib.sha1(b"blob %d\0" % len(data) + data).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, scaled by the copy-kernel calibration it records;
+    None when the kernel source has changed since the counters were taken."""
+    tfile = os.path.join(ROOT, "profiles", "sweep_kernel_section_36to35_traffic.json")
+    if not os.path.exists(tfile):
+        return None
+    with open(tfile) as f:
+        t = json.load(f)
+    src = os.path.join(ROOT, t.get("kernel_source", ""))
+    if not os.path.exists(src) or _blob_sha(src) != t.get("kernel_source_blob"):
+        return None
+    return t.get("bytes_per_launch")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,7 +89,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other workloads (endgame batches, uneven layers)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 512 MiB device copy (counter calibration)")
+                    help="also run a 512 MiB fill and a 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: sharding the sweep over several GPUs "
@@ -130,11 +153,7 @@ def main():
     # every child superinfo read once
     alg_bytes = 64 * entries + 64 * centries
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "sweep_traffic.json")
-    if os.path.exists(tfile):
-        with open(tfile) as f:
-            traffic = json.load(f).get("bytes_per_launch")
+    traffic = measured_traffic()
 
     res = {
         "metric": METRIC,
