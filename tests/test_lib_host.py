@@ -100,6 +100,22 @@ def test_rmax_matches_definition():
             assert np.array_equal(got, want)
 
 
+def test_rmax_parity_split():
+    """rmax at elements of even total turn count reads only odd elements and
+    vice versa (every single-quadrant turn changes the parity): changing the
+    input on one parity class leaves rmax on that class unchanged."""
+    rng = np.random.default_rng(6)
+    parity = np.array([sum((g >> (2 * j)) & 3 for j in range(4)) & 1 for g in range(256)])
+    for _ in range(50):
+        x = rng.random(256) < 0.2
+        y = x.copy()
+        flip = (parity == 0) & (rng.random(256) < 0.5)
+        y[flip] = ~y[flip]
+        rx = bits_of(P.pentago_debug_rmax(words_of(x)))
+        ry = bits_of(P.pentago_debug_rmax(words_of(y)))
+        assert np.array_equal(rx[parity == 0], ry[parity == 0])
+
+
 def test_shift_matches_definition():
     rng = np.random.default_rng(6)
     for _ in range(40):
