@@ -13,6 +13,10 @@
                  stones (first 4096 dropped as warm-up) against the server
                  holding every section solved above resident; p50/p99 latency
                  and queries/s, against one query per launch.
+  serving_resident
+                 2^16 queries drawn from the resident sections (random
+                 quadrant turns), answered by lookup: alone, and mixed one to
+                 one with random-play queries under Poisson arrivals.
 Inputs are resident on the GPU when timing starts; times are HIP events on
 the launch stream.
 """
@@ -172,15 +176,69 @@ def serving(P, torch, stream, resident, queries):
             "plain_answers_equal_served": same, "warmup_dropped": warm}
 
 
+def serving_resident(P, torch, stream, resident, queries):
+    """Queries drawn from the resident sections (uniform section, uniform
+    entry, every quadrant turned at random) answered by table lookup: alone
+    at full speed, and mixed one to one with the random-play stream under
+    Poisson arrivals at 0.7 of the mix's measured capacity."""
+    shapes = [P.pentago_section_shape(c)[0] for c, _ in resident]
+    n = 1 << 16
+    sec, idx = I.resident_entries(shapes, n, seed=I.SEED_SERVE + 2)
+    codes = np.array([P.pentago_section_board(resident[s][0], i) for s, i in zip(sec, idx)], np.uint16)
+    looked = P.boards_to_codes(I.turn_quadrants(I.codes_to_boards(codes), seed=I.SEED_SERVE + 3))
+    srv = P.Server(memory_budget=4 << 30, max_inflight=1 << 20, max_batch=4096, streams=4)
+    for counts, table in resident:
+        srv.add_section(counts, table)
+    out = {}
+    # lookups alone, everything arriving at once
+    srv.replay(looked[:4096], np.zeros(4096))
+    srv.reset_stats()
+    t0 = time.perf_counter()
+    got = srv.replay(looked, np.zeros(n))
+    dt = time.perf_counter() - t0
+    st = srv.stats()
+    # the same boards solved by the endgame search (resident sections have
+    # at most 3 empty cells): the lookups must give the same bytes
+    dev = torch.from_numpy(looked.view(np.int16).copy()).cuda()
+    ref = torch.empty((n, 8), dtype=torch.int64, device="cuda")
+    P.pentago_eval_batch(dev, ref, None, stream)
+    torch.cuda.synchronize()
+    same = bool(np.array_equal(ref.cpu().numpy().view(np.uint64), got))
+    out["lookup_only"] = {"queries": int(st["queries"]), "lookups": int(st["lookups"]),
+                          "queries_per_s": n / dt, "p50_us": st["p50_us"], "p99_us": st["p99_us"],
+                          "answers_equal_search": same}
+    # one to one with random-play queries
+    rp = P.boards_to_codes(queries[:n])
+    mix = np.empty((2 * n, 4), np.uint16)
+    mix[0::2] = looked
+    mix[1::2] = rp
+    t0 = time.perf_counter()
+    srv.reset_stats()
+    srv.replay(mix, np.zeros(len(mix)))
+    cap = len(mix) / (time.perf_counter() - t0)
+    arrivals = I.poisson_arrivals(len(mix), 0.7 * cap, seed=I.SEED_SERVE + 4)
+    srv.reset_stats()
+    srv.replay(mix, arrivals)
+    st = srv.stats()
+    srv.close()
+    out["mixed"] = {"queries": int(st["queries"]), "lookups": int(st["lookups"]), "searches": int(st["searches"]),
+                    "saturated_queries_per_s": cap, "offered_rate_per_s": 0.7 * cap,
+                    "p50_us": st["p50_us"], "p99_us": st["p99_us"], "queries_per_s": st["queries_per_s"],
+                    "lookup_p50_us": st["lookup_p50_us"], "lookup_p99_us": st["lookup_p99_us"],
+                    "search_p50_us": st["search_p50_us"], "search_p99_us": st["search_p99_us"]}
+    return out
+
+
 def run_all(P, torch, stream, boards_2p20=None, serve_queries=None, resident=None):
     res = {}
     for name, fn in (("endgame_4096", lambda: endgame(P, torch, stream, I.random_placement_boards(4096, 17, 16), False)),
                      ("endgame_2p20", lambda: endgame(P, torch, stream, boards_2p20, True)),
                      ("layers", lambda: layers(P, torch, stream, resident)),
-                     ("serving", lambda: serving(P, torch, stream, resident, serve_queries))):
+                     ("serving", lambda: serving(P, torch, stream, resident, serve_queries)),
+                     ("serving_resident", lambda: serving_resident(P, torch, stream, resident, serve_queries))):
         if name == "endgame_2p20" and boards_2p20 is None:
             continue
-        if name == "serving" and serve_queries is None:
+        if name.startswith("serving") and serve_queries is None:
             continue
         t0 = time.perf_counter()
         try:

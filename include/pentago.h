@@ -199,6 +199,8 @@ typedef struct {
     uint64_t batches;        /* device batches launched */
     double p50_us, p99_us;   /* latency from submit to result visible on the host */
     double queries_per_s;    /* answered queries over the time since the first submit */
+    double lookup_p50_us, lookup_p99_us;  /* the same, lookups only (0 if none) */
+    double search_p50_us, search_p99_us;  /* the same, searches only (0 if none) */
 } pentago_serve_stats;
 
 /* Create a server on the current device.  A background thread batches
@@ -217,7 +219,10 @@ int pentago_serve_add_section(pentago_server *srv, pentago_section s,
  * for an invalid board; ERANGE for more than 10 empty cells on a board that
  * no resident section holds.  A batch is admitted when a stream is idle and
  * its device scratch fits memory_budget next to the batches running (a
- * batch is always admitted when nothing runs, so no query waits forever). */
+ * batch is always admitted when nothing runs, so no query waits forever).
+ * Lookups are admitted before searches; with two or more streams the first
+ * stream runs lookups only, so lookups never queue behind search batches;
+ * among searches the class (empties group) with the oldest query goes first. */
 int pentago_serve_submit(pentago_server *srv, pentago_board board, uint64_t *ticket);
 
 /* Fetch the result of a ticket into host memory.  EAGAIN while pending;

@@ -85,7 +85,7 @@ struct pentago_server {
     std::condition_variable cv;
     int worker_error = 0;
     // statistics
-    std::vector<double> lat_us;
+    std::vector<double> lat_us, lat_lookup_us, lat_search_us;
     uint64_t nqueries = 0, nlookups = 0, nsearches = 0, nbatches = 0;
     Clock::time_point t_first;
     Clock::time_point t_last;
@@ -104,7 +104,9 @@ void publish(pentago_server *S, Batch &B)
         memcpy(&r, h + 4 * i, sizeof(r));
         S->results[B.qs[i].ticket] = r;
         S->live[B.qs[i].ticket] = 1;
-        S->lat_us.push_back(std::chrono::duration<double, std::micro>(now - B.qs[i].t_submit).count());
+        const double us = std::chrono::duration<double, std::micro>(now - B.qs[i].t_submit).count();
+        S->lat_us.push_back(us);
+        (B.cls == 0 ? S->lat_lookup_us : S->lat_search_us).push_back(us);
         S->nqueries++;
         (B.cls == 0 ? S->nlookups : S->nsearches)++;
     }
@@ -154,21 +156,27 @@ void worker_loop(pentago_server *S)
                 progress = true;
             }
         }
-        // 2. admissions: oldest class first, while a stream is idle and memory allows
+        // 2. admissions, while a stream is idle and memory allows: lookups
+        //    first (they take microseconds), then the oldest search class.
+        //    With two or more streams, stream 0 runs lookups only, so a
+        //    lookup never waits behind a search batch.
         for (size_t i = 0; i < nst; i++) {
             if (S->busy[i]) continue;
             Batch &B = S->running[i];
             {
                 std::lock_guard<std::mutex> lock(S->mu);
                 int best = -1;
-                for (int c = 0; c < kClasses; c++)
-                    if (!S->pending[c].empty() &&
-                        (best < 0 || S->pending[c].front().t_submit < S->pending[best].front().t_submit))
-                        best = c;
-                if (best < 0) break;
+                if (!S->pending[0].empty()) best = 0;
+                else if (i > 0 || nst == 1) {
+                    for (int c = 1; c < kClasses; c++)
+                        if (!S->pending[c].empty() &&
+                            (best < 0 || S->pending[c].front().t_submit < S->pending[best].front().t_submit))
+                            best = c;
+                }
+                if (best < 0) continue;
                 const size_t take = std::min<size_t>(S->pending[best].size(), S->cfg.max_batch);
                 const size_t need = best == 0 ? 0 : eval_scratch_bytes(take, S->grid, best == 4);
-                if (S->scratch_in_use + need > S->cfg.memory_budget && S->scratch_in_use > 0) break;
+                if (S->scratch_in_use + need > S->cfg.memory_budget && S->scratch_in_use > 0) continue;
                 B.cls = best;
                 B.qs.assign(S->pending[best].begin(), S->pending[best].begin() + take);
                 S->pending[best].erase(S->pending[best].begin(), S->pending[best].begin() + take);
@@ -368,11 +376,16 @@ int pentago_serve_stats_get(pentago_server *srv, pentago_serve_stats *st)
     st->lookups = srv->nlookups;
     st->searches = srv->nsearches;
     st->batches = srv->nbatches;
-    if (!srv->lat_us.empty()) {
-        std::vector<double> v = srv->lat_us;
+    auto pct = [](std::vector<double> v, double *p50, double *p99) {
+        if (v.empty()) return;
         std::sort(v.begin(), v.end());
-        st->p50_us = v[(v.size() - 1) / 2];
-        st->p99_us = v[(size_t)((v.size() - 1) * 0.99)];
+        *p50 = v[(v.size() - 1) / 2];
+        *p99 = v[(size_t)((v.size() - 1) * 0.99)];
+    };
+    pct(srv->lat_lookup_us, &st->lookup_p50_us, &st->lookup_p99_us);
+    pct(srv->lat_search_us, &st->search_p50_us, &st->search_p99_us);
+    if (!srv->lat_us.empty()) {
+        pct(srv->lat_us, &st->p50_us, &st->p99_us);
         const double span = std::chrono::duration<double>(srv->t_last - srv->t_first).count();
         st->queries_per_s = span > 0 ? srv->nqueries / span : 0;
     }
@@ -384,6 +397,8 @@ int pentago_serve_reset_stats(pentago_server *srv)
     if (!srv) return fail(PENTAGO_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> lock(srv->mu);
     srv->lat_us.clear();
+    srv->lat_lookup_us.clear();
+    srv->lat_search_us.clear();
     srv->nqueries = srv->nlookups = srv->nsearches = srv->nbatches = 0;
     srv->any = false;
     return 0;

@@ -193,6 +193,43 @@ def _play_chunk(args):
     return out
 
 
+def codes_to_boards(codes):
+    """(n, 4) quadrant codes (base 3, digit = 3 * (r % 3) + c % 3 of the
+    quadrant's cell) -> (n, 36) uint8 cell arrays."""
+    codes = np.asarray(codes, dtype=np.int64).reshape(-1, 4)
+    boards = np.zeros((len(codes), 6, 6), np.uint8)
+    digits = (codes[:, :, None] // (3 ** np.arange(9))[None, None, :]) % 3
+    for j in range(4):
+        r0, c0 = 3 * (j // 2), 3 * (j % 2)
+        boards[:, r0:r0 + 3, c0:c0 + 3] = digits[:, j, :].reshape(-1, 3, 3)
+    return boards.reshape(-1, 36)
+
+
+def turn_quadrants(boards, seed):
+    """Every quadrant of every board turned by an independent uniform number
+    of quarter turns (numpy.rot90 of the 3x3 sub-array)."""
+    rng = np.random.default_rng(seed)
+    b = np.array(boards, dtype=np.uint8).reshape(-1, 6, 6)
+    k = rng.integers(0, 4, size=(len(b), 4))
+    for j in range(4):
+        r0, c0 = 3 * (j // 2), 3 * (j % 2)
+        for t in range(1, 4):
+            sel = k[:, j] == t
+            if sel.any():
+                b[sel, r0:r0 + 3, c0:c0 + 3] = np.rot90(b[sel, r0:r0 + 3, c0:c0 + 3], t, axes=(1, 2))
+    return b.reshape(-1, 36)
+
+
+def resident_entries(section_sizes, n, seed):
+    """n (section number, entry number) pairs: a uniform section, then a
+    uniform entry of it.  section_sizes: the shape (4 extents) of each."""
+    rng = np.random.default_rng(seed)
+    sec = rng.integers(0, len(section_sizes), size=n)
+    idx = np.stack([rng.integers(0, np.array([section_sizes[s][j] for s in sec]))
+                    for j in range(4)], axis=1)
+    return sec, idx
+
+
 def poisson_arrivals(n, rate, seed=SEED_SERVE):
     """Arrival times (seconds) of an open-loop Poisson stream."""
     rng = np.random.default_rng(seed + 1)

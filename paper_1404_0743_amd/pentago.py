@@ -47,7 +47,9 @@ class ServeStats(ctypes.Structure):
     _fields_ = [("queries", ctypes.c_uint64), ("lookups", ctypes.c_uint64),
                 ("searches", ctypes.c_uint64), ("batches", ctypes.c_uint64),
                 ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
-                ("queries_per_s", ctypes.c_double)]
+                ("queries_per_s", ctypes.c_double),
+                ("lookup_p50_us", ctypes.c_double), ("lookup_p99_us", ctypes.c_double),
+                ("search_p50_us", ctypes.c_double), ("search_p99_us", ctypes.c_double)]
 
 
 _lib = None
