@@ -978,20 +978,32 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
     }
 }
 
-// Count roots per number of empty cells (index 11: invalid boards).
-__global__ void eval_count_kernel(const uint64_t *boards, size_t n, int *count, uint8_t *empties,
-                                  int *status, uint4 *out)
+// Count roots per number of empty cells (index 11: invalid boards).  Counts
+// are gathered per workgroup in LDS first, so each workgroup adds to the
+// global counters once per bin (a million lanes adding to twelve global
+// counters directly serialise on them).
+__global__ void __launch_bounds__(256)
+    eval_count_kernel(const uint64_t *boards, size_t n, int *count, uint8_t *empties, int *status,
+                      uint4 *out)
 {
+    __shared__ int lc[12];
+    if (threadIdx.x < 12) lc[threadIdx.x] = 0;
+    __syncthreads();
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const RootInfo R = decode_root(boards[i]);
-    const int e = R.valid ? R.e : 11;
-    empties[i] = (uint8_t)e;
-    atomicAdd(&count[e], 1);
-    if (!R.valid) {
-        const uint4 z = make_uint4(0, 0, 0, 0);
-        out[4 * i] = z; out[4 * i + 1] = z; out[4 * i + 2] = z; out[4 * i + 3] = z;
-        if (status) atomicAdd(status, 1);
+    if (i < n) {
+        const RootInfo R = decode_root(boards[i]);
+        const int e = R.valid ? R.e : 11;
+        empties[i] = (uint8_t)e;
+        atomicAdd(&lc[e], 1);
+        if (!R.valid) {
+            const uint4 z = make_uint4(0, 0, 0, 0);
+            out[4 * i] = z; out[4 * i + 1] = z; out[4 * i + 2] = z; out[4 * i + 3] = z;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 12 && lc[threadIdx.x]) {
+        atomicAdd(&count[threadIdx.x], lc[threadIdx.x]);
+        if (threadIdx.x == 11 && status) atomicAdd(status, lc[11]);
     }
 }
 
@@ -1009,15 +1021,21 @@ __global__ void eval_scan_kernel(const int *count, int *start, int *cursor)
     cursor[11] = 0;
 }
 
-__global__ void eval_scatter_kernel(const uint8_t *empties, size_t n, const int *start, int *cursor,
-                                    int *order)
+// Roots into their bins: positions inside the workgroup from LDS counters,
+// one global reservation per bin per workgroup.
+__global__ void __launch_bounds__(256)
+    eval_scatter_kernel(const uint8_t *empties, size_t n, const int *start, int *cursor, int *order)
 {
+    __shared__ int lc[11], base[11];
+    if (threadIdx.x < 11) lc[threadIdx.x] = 0;
+    __syncthreads();
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int e = empties[i];
-    if (e > 10) return;
-    const int pos = atomicAdd(&cursor[e], 1);
-    order[start[e] + pos] = (int)i;
+    const int e = i < n ? empties[i] : 11;
+    const int local = e <= 10 ? atomicAdd(&lc[e], 1) : 0;
+    __syncthreads();
+    if (threadIdx.x < 11 && lc[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], lc[threadIdx.x]);
+    __syncthreads();
+    if (e <= 10) order[start[e] + base[e] + local] = (int)i;
 }
 
 __global__ void zero_ints_kernel(int *p, int n)
