@@ -222,7 +222,9 @@ int pentago_serve_add_section(pentago_server *srv, pentago_section s,
  * batch is always admitted when nothing runs, so no query waits forever).
  * Lookups are admitted before searches; with two or more streams the first
  * stream runs lookups only, so lookups never queue behind search batches;
- * among searches the class (empties group) with the oldest query goes first. */
+ * among searches the class (empties group) with the oldest query goes first,
+ * with at most one batch in flight per class (a class's queue grows while
+ * its batch runs, so batch sizes follow the load). */
 int pentago_serve_submit(pentago_server *srv, pentago_board board, uint64_t *ticket);
 
 /* Fetch the result of a ticket into host memory.  EAGAIN while pending;

@@ -76,6 +76,8 @@ struct pentago_server {
     // queues
     std::mutex mu;
     std::deque<Query> pending[kClasses];
+    std::atomic<size_t> npending{0};  // total over the classes (read without the lock)
+    int class_running[kClasses] = {};  // batches in flight per search class
     std::unordered_map<uint64_t, pentago_superinfo> results;
     std::unordered_map<uint64_t, int> live;  // ticket -> 0 pending, 1 done
     uint64_t next_ticket = 1;
@@ -83,6 +85,7 @@ struct pentago_server {
     std::thread worker;
     std::atomic<bool> stop{false};
     std::condition_variable cv;
+    std::condition_variable done_cv;  // notified when a batch's results are published
     int worker_error = 0;
     // statistics
     std::vector<double> lat_us, lat_lookup_us, lat_search_us;
@@ -113,6 +116,8 @@ void publish(pentago_server *S, Batch &B)
     S->t_last = now;
     S->nbatches++;
     S->scratch_in_use -= B.scratch;
+    S->class_running[B.cls]--;
+    S->done_cv.notify_all();
 }
 
 // Launch a batch on stream si: boards up, lookup or search kernels, results down.
@@ -162,14 +167,18 @@ void worker_loop(pentago_server *S)
         //    lookup never waits behind a search batch.
         for (size_t i = 0; i < nst; i++) {
             if (S->busy[i]) continue;
+            if (S->npending.load(std::memory_order_relaxed) == 0) break;
             Batch &B = S->running[i];
             {
                 std::lock_guard<std::mutex> lock(S->mu);
                 int best = -1;
                 if (!S->pending[0].empty()) best = 0;
                 else if (i > 0 || nst == 1) {
+                    // one batch in flight per search class: under load the
+                    // class's queue grows while its batch runs, so batches
+                    // grow with the load instead of fragmenting
                     for (int c = 1; c < kClasses; c++)
-                        if (!S->pending[c].empty() &&
+                        if (!S->pending[c].empty() && S->class_running[c] == 0 &&
                             (best < 0 || S->pending[c].front().t_submit < S->pending[best].front().t_submit))
                             best = c;
                 }
@@ -178,8 +187,10 @@ void worker_loop(pentago_server *S)
                 const size_t need = best == 0 ? 0 : eval_scratch_bytes(take, S->grid, best == 4);
                 if (S->scratch_in_use + need > S->cfg.memory_budget && S->scratch_in_use > 0) continue;
                 B.cls = best;
+                S->class_running[best]++;
                 B.qs.assign(S->pending[best].begin(), S->pending[best].begin() + take);
                 S->pending[best].erase(S->pending[best].begin(), S->pending[best].begin() + take);
+                S->npending.fetch_sub(take, std::memory_order_relaxed);
                 B.scratch = need;
                 S->scratch_in_use += need;
             }
@@ -187,8 +198,10 @@ void worker_loop(pentago_server *S)
             if (launch_batch(S, (int)i, B) != 0) {
                 std::lock_guard<std::mutex> lock(S->mu);
                 S->worker_error = PENTAGO_EDEVICE;
+                S->done_cv.notify_all();
                 for (const Query &q : B.qs) S->live.erase(q.ticket);
                 S->scratch_in_use -= B.scratch;
+                S->class_running[B.cls]--;
                 B.qs.clear();
                 continue;
             }
@@ -347,6 +360,7 @@ int pentago_serve_submit(pentago_server *srv, pentago_board board, uint64_t *tic
         srv->t_first = q.t_submit;
     }
     srv->pending[q.cls].push_back(q);
+    srv->npending.fetch_add(1, std::memory_order_relaxed);
     *ticket = q.ticket;
     srv->cv.notify_one();
     return 0;
@@ -412,16 +426,26 @@ int pentago_serve_replay(pentago_server *srv, const pentago_board *boards, const
     std::vector<std::atomic<int>> ready(n);
     for (size_t i = 0; i < n; i++) ready[i].store(0);
     std::atomic<int> err{0};
+    // results are collected in submission order; the collector sleeps on the
+    // server's completion signal instead of polling
     std::thread poller([&] {
         for (size_t i = 0; i < n && !err.load(); i++) {
             while (!ready[i].load() && !err.load()) std::this_thread::yield();
             if (err.load()) break;
-            for (;;) {
-                const int rc = pentago_serve_poll(srv, tickets[i], &results[i]);
-                if (rc == 0) break;
-                if (rc != PENTAGO_EAGAIN) { err.store(rc); break; }
-                std::this_thread::yield();
+            std::unique_lock<std::mutex> lock(srv->mu);
+            srv->done_cv.wait(lock, [&] {
+                auto it = srv->live.find(tickets[i]);
+                return srv->worker_error != 0 || it == srv->live.end() || it->second != 0;
+            });
+            auto it = srv->live.find(tickets[i]);
+            if (it == srv->live.end() || it->second == 0) {
+                err.store(srv->worker_error ? srv->worker_error : PENTAGO_EINVAL);
+                break;
             }
+            results[i] = srv->results[tickets[i]];
+            srv->results.erase(tickets[i]);
+            srv->live.erase(it);
+            srv->inflight--;
         }
     });
     const Clock::time_point t0 = Clock::now();
