@@ -51,15 +51,22 @@ int device_tables(DevTables *out)
     DevTables T;
     memset(&T, 0, sizeof(T));
     std::vector<uint32_t> nodes;
-    std::vector<uint16_t> ranks;
+    std::vector<uint16_t> ranks, submask, subrank;
     for (int k = 0; k <= 10; k++) {
         const DagLayout &L = dag_layout(k);
         T.dag_node_off[k] = (int)nodes.size();
         T.dag_rank_off[k] = (int)ranks.size();
+        T.dag_sub_off[k] = (int)submask.size();
         nodes.insert(nodes.end(), L.node.begin(), L.node.end());
         ranks.insert(ranks.end(), L.rank.begin(), L.rank.end());
-        for (int t = 0; t < 12; t++) T.dag_layer[k][t] = t <= k + 1 ? L.layer_start[t] : 0;
+        submask.insert(submask.end(), L.sub_mask.begin(), L.sub_mask.end());
+        subrank.insert(subrank.end(), L.sub_rank.begin(), L.sub_rank.end());
+        for (int t = 0; t < 12; t++) {
+            T.dag_layer[k][t] = t <= k + 1 ? L.layer_start[t] : 0;
+            T.dag_sub_start[k][t] = t <= k + 1 ? L.sub_start[t] : 0;
+        }
         T.dag_max[k] = L.max_layer;
+        T.dag_sub_max[k] = L.max_subsets;
     }
     void *p;
     struct Up {
@@ -67,7 +74,7 @@ int device_tables(DevTables *out)
         size_t bytes;
         void **dst;
     };
-    void *canon, *qinfo, *lm, *dn, *dr, *sel, *cref, *uref;
+    void *canon, *qinfo, *lm, *dn, *dr, *sel, *cref, *uref, *smask, *srank;
     Up ups[] = {{H.canon.data(), H.canon.size() * 2, &canon},
                 {H.qinfo.data(), H.qinfo.size() * sizeof(QInfo), &qinfo},
                 {H.lm.data(), H.lm.size() * sizeof(LineMasks), &lm},
@@ -75,7 +82,9 @@ int device_tables(DevTables *out)
                 {ranks.data(), ranks.size() * 2, &dr},
                 {H.sel.data(), H.sel.size() * 4, &sel},
                 {H.chunk_ref.data(), H.chunk_ref.size() * 2, &cref},
-                {H.u_ref.data(), H.u_ref.size() * 4, &uref}};
+                {H.u_ref.data(), H.u_ref.size() * 4, &uref},
+                {submask.data(), submask.size() * 2, &smask},
+                {subrank.data(), subrank.size() * 2, &srank}};
     for (Up &u : ups) {
         e = hipMalloc(&p, u.bytes);
         if (e != hipSuccess) return hip_fail(e, "hipMalloc(tables)");
@@ -91,6 +100,8 @@ int device_tables(DevTables *out)
     T.sel = (const uint4 *)sel;
     T.chunk_ref = (const uint16_t *)cref;
     T.u_ref = (const uint32_t *)uref;
+    T.dag_sub_mask = (const uint16_t *)smask;
+    T.dag_sub_rank = (const uint16_t *)srank;
     g_dev_tables[dev] = T;
     *out = T;
     return 0;

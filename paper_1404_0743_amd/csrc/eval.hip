@@ -58,7 +58,7 @@ static int eval_alloc(size_t n, int grid, hipStream_t st, EvalAlloc *A)
 {
     const size_t ints = 64;
     const size_t glayer = (size_t)grid * 2 * kDagGlobalLayer * 64;
-    const size_t bytes = glayer + ints * 4 + 16 + n * 4 + n + 256;
+    const size_t bytes = glayer + ints * 4 + 32 + n * 4 + n + 256;
     hipError_t e = hipMallocAsync(&A->base, bytes, st);
     if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(eval scratch)");
     char *p = (char *)A->base;
@@ -68,8 +68,8 @@ static int eval_alloc(size_t n, int grid, hipStream_t st, EvalAlloc *A)
     A->S.start = A->S.count + 16;
     A->S.cursor = A->S.count + 32;
     p += ints * 4;
-    A->S.counter = (unsigned long long *)p;
-    p += 16;
+    A->S.counter = (unsigned long long *)p;  // one work-queue counter per persistent class
+    p += 32;
     A->S.order = (int *)p;
     p += n * 4;
     A->S.empties = (uint8_t *)p;
@@ -81,7 +81,7 @@ static int eval_alloc(size_t n, int grid, hipStream_t st, EvalAlloc *A)
 // 10 empty cells and needs the global layer buffers).
 size_t eval_scratch_bytes(size_t n, int grid, bool deep)
 {
-    return (deep ? (size_t)grid * 2 * kDagGlobalLayer * 64 : 0) + 64 * 4 + 16 + n * 5 + 256;
+    return (deep ? (size_t)grid * 2 * kDagGlobalLayer * 64 : 0) + 64 * 4 + 32 + n * 5 + 256;
 }
 
 // Enqueue one endgame batch on st with stream-ordered scratch.

@@ -23,6 +23,11 @@ struct DevTables {
     int dag_rank_off[11];       // start of layout e in dag_rank
     int dag_layer[11][12];      // layer starts (relative) of layout e
     int dag_max[11];            // largest layer of layout e
+    const uint16_t *dag_sub_mask;  // subsets of the e slots by size, all e back to back
+    const uint16_t *dag_sub_rank;  // rank of a subset within its size, all e back to back
+    int dag_sub_off[11];        // start of layout e in both (2^e entries each)
+    int dag_sub_start[11][12];  // start of size s within layout e
+    int dag_sub_max[11];        // largest C(e, s)
 };
 
 // One section sweep (Section IV): a parent section, its child sections and
@@ -83,6 +88,7 @@ hipError_t launch_eval_group(const uint64_t *boards, int e, int first, int count
                              const EvalScratch &S, const DevTables &T, hipStream_t s);
 
 int dag_lds_bytes(int e);
+int dag_ftab_bytes(int e);
 
 // A solved section kept resident for lookups.
 struct ResidentSection {

@@ -830,9 +830,13 @@ hipError_t launch_sweep_batch(const SweepJob *dev_jobs, const long long *dev_til
 // B = F_parent(node) | rmax(not W) (64 B) in a layer buffer.
 // ---------------------------------------------------------------------------
 
+// Per root: two layers of node records (64 B each), then the layer's
+// five-set tables (two colours x the largest C(e, s) subsets, 32 B each).
+int dag_ftab_bytes(int e) { return 2 * dag_layout(e).max_subsets * 32; }
+
 int dag_lds_bytes(int e)
 {
-    return 2 * dag_layout(e).max_layer * 64;
+    return 2 * dag_layout(e).max_layer * 64 + dag_ftab_bytes(e);
 }
 
 struct RootInfo {
@@ -882,10 +886,18 @@ __device__ __forceinline__ void wave_sync()
 
 // Solve one root with a group of GROUP threads: the whole workgroup (256) or
 // one wave (64).  `buf0` and `buf1` hold two layers of A/B records (64 B per
-// node); slot_q/slot_l (10 ints each, LDS) the root's empty cells.
+// node); `ftab` the five-set tables of the current layer; slot_q/slot_l (10
+// ints each, LDS) the root's empty cells.
+//
+// Five-sets: the nodes of layer t hold ceil(t/2) stones of the root's mover
+// and floor(t/2) of the other side in the root's empty cells, and a colour's
+// five-set depends only on which cells hold that colour.  So each layer first
+// computes the five-set of every subset of the empty cells of those two sizes
+// (C(e, s) boards per colour instead of one per node and colour: 581 boards
+// against 4246 for 8 empty cells), and each node reads its two.
 template <int GROUP>
 __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, uint4 *buf1,
-                           uint4 *out, int *s_slot_q, int *s_slot_l)
+                           uint4 *ftab, uint4 *out, int *s_slot_q, int *s_slot_l)
 {
     const int lane = GROUP == 256 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
     if (lane == 0) {
@@ -905,36 +917,59 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
     const int e = R.e;
     const uint32_t *nodes = T.dag_node + T.dag_node_off[e];
     const uint16_t *rank = T.dag_rank + T.dag_rank_off[e];
+    const uint16_t *smask = T.dag_sub_mask + T.dag_sub_off[e];
+    const uint16_t *srank = T.dag_sub_rank + T.dag_sub_off[e];
     const int *layer = T.dag_layer[e];
+    const int smax = T.dag_sub_max[e];
+    // the root mover's stones and the other side's, per quadrant
+    unsigned cm0[4], om0[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        cm0[j] = R.mover == 1 ? R.bm[j] : R.wm[j];
+        om0[j] = R.mover == 1 ? R.wm[j] : R.bm[j];
+    }
     uint4 *cur = buf0, *prev = buf1;
     for (int t = e; t >= 0; t--) {
         const int n0 = layer[t], n1 = layer[t + 1];
         const int x = (t & 1) ? 3 - R.mover : R.mover;   // side to move at layer t
         const int xdigit = (t & 1) ? 2 : 1;              // slot digit of x's stones
+        // five-set tables of the layer: entries [0, nc) for the root mover's
+        // subsets of size ceil(t/2), [smax, smax + no) for the other side's
+        const int sc = (t + 1) >> 1, so = t >> 1;
+        const int nc = T.dag_sub_start[e][sc + 1] - T.dag_sub_start[e][sc];
+        const int no = T.dag_sub_start[e][so + 1] - T.dag_sub_start[e][so];
+        for (int i = lane; i < nc + no; i += GROUP) {
+            const bool mine = i < nc;
+            const int r = mine ? i : i - nc;
+            const unsigned m = smask[T.dag_sub_start[e][mine ? sc : so] + r];
+            unsigned xm[4] = {mine ? cm0[0] : om0[0], mine ? cm0[1] : om0[1], mine ? cm0[2] : om0[2],
+                              mine ? cm0[3] : om0[3]};
+            for (int sl = 0; sl < e; sl++)
+                if ((m >> sl) & 1) {
+                    const int q = s_slot_q[sl];
+                    const unsigned bit = 1u << s_slot_l[sl];
+                    xm[0] |= q == 0 ? bit : 0u;
+                    xm[1] |= q == 1 ? bit : 0u;
+                    xm[2] |= q == 2 ? bit : 0u;
+                    xm[3] |= q == 3 ? bit : 0u;
+                }
+            const Set256 F = board_five(T, xm);
+            uint4 *dst = ftab + 2 * ((mine ? 0 : smax) + r);
+            dst[0] = make_uint4(F.w[0], F.w[1], F.w[2], F.w[3]);
+            dst[1] = make_uint4(F.w[4], F.w[5], F.w[6], F.w[7]);
+        }
+        if (GROUP == 256) __syncthreads();
+        else wave_sync();
         for (int i = n0 + lane; i < n1; i += GROUP) {
             const uint32_t nd = nodes[i];
             const unsigned cmask = nd & 0xffffu, omask = nd >> 16;
-            unsigned bm[4] = {R.bm[0], R.bm[1], R.bm[2], R.bm[3]};
-            unsigned wm[4] = {R.wm[0], R.wm[1], R.wm[2], R.wm[3]};
             int code = 0;
-            for (int s = e - 1; s >= 0; s--) {
-                const int q = s_slot_q[s], l = s_slot_l[s];
-                const bool isc = (cmask >> s) & 1, iso = (omask >> s) & 1;
-                // root mover's stones are black iff the root mover is black
-                const bool black = (isc && R.mover == 1) || (iso && R.mover == 2);
-                const bool white = (isc && R.mover == 2) || (iso && R.mover == 1);
-                bm[q] |= (unsigned)black << l;
-                wm[q] |= (unsigned)white << l;
-                code = 3 * code + (isc ? 1 : iso ? 2 : 0);
-            }
-            unsigned xm[4], ym[4];
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                xm[j] = x == 1 ? bm[j] : wm[j];
-                ym[j] = x == 1 ? wm[j] : bm[j];
-            }
-            const Set256 Fx = board_five(T, xm);
-            const Set256 Fy = board_five(T, ym);
+            for (int sl = e - 1; sl >= 0; sl--)
+                code = 3 * code + (((cmask >> sl) & 1) ? 1 : ((omask >> sl) & 1) ? 2 : 0);
+            const Set256 Fc = set_from(ftab + 2 * srank[cmask]);
+            const Set256 Fo = set_from(ftab + 2 * (smax + srank[omask]));
+            const Set256 &Fx = x == R.mover ? Fc : Fo;
+            const Set256 &Fy = x == R.mover ? Fo : Fc;
             Set256 Wnt = s_zero(), Nnt = s_zero();
             if (t == e) {
                 Nnt = s_full();
@@ -942,18 +977,12 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
                 const unsigned free = ~(cmask | omask) & ((1u << e) - 1u);
                 unsigned f = free;
                 while (f) {
-                    const int s = __builtin_ctz(f);
+                    const int sl = __builtin_ctz(f);
                     f &= f - 1;
-                    const int ci = rank[code + xdigit * (int)c_pow3[s]];
+                    const int ci = rank[code + xdigit * (int)c_pow3[sl]];
                     const uint4 *p = prev + 4 * ci;
-                    Set256 A, B;
-                    const uint4 a0 = p[0], a1 = p[1], b0 = p[2], b1 = p[3];
-                    A.w[0] = a0.x; A.w[1] = a0.y; A.w[2] = a0.z; A.w[3] = a0.w;
-                    A.w[4] = a1.x; A.w[5] = a1.y; A.w[6] = a1.z; A.w[7] = a1.w;
-                    B.w[0] = b0.x; B.w[1] = b0.y; B.w[2] = b0.z; B.w[3] = b0.w;
-                    B.w[4] = b1.x; B.w[5] = b1.y; B.w[6] = b1.z; B.w[7] = b1.w;
-                    s_or_into(Wnt, A);
-                    s_or_into(Nnt, B);
+                    s_or_into(Wnt, set_from(p));
+                    s_or_into(Nnt, set_from(p + 2));
                 }
             }
             Set256 W, N;
@@ -1043,14 +1072,20 @@ __global__ void zero_ints_kernel(int *p, int n)
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
-// Persistent solve over all valid roots, most empty cells first, from two
-// device work queues: roots with more than kWaveMaxEmpties empty cells are
-// solved by a whole workgroup each (those with 9 or 10 keep their layers in
-// the workgroup's slot of a global buffer, the rest in LDS); the rest by one
-// wave each, four at a time per workgroup, synchronised per wave only.
+// Persistent solve over all valid roots, most empty cells first.  The roots
+// are binned by number of empty cells on the device; three persistent
+// launches follow one another on the stream, one per LDS class, each taking
+// roots from its own device work queue (no host synchronisation):
+//   class 0: 8 to 10 empty cells, a workgroup per root (9 and 10 keep their
+//            layers in the workgroup's slot of a global buffer);
+//   class 1: 7 empty cells, a workgroup per root, a smaller LDS footprint;
+//   class 2: up to kWaveMaxEmpties, one wave per root, four per workgroup,
+//            synchronised per wave only.
 constexpr int kWaveMaxEmpties = 6;
-constexpr int kWaveLdsBytes = 2 * 90 * 64;  // two layers of the widest 6-empty layer
+// two layers of the widest 6-empty layer, then the five-set tables (C(6,3) = 20)
+constexpr int kWaveLdsBytes = 2 * 90 * 64 + 2 * 20 * 32;
 
+template <int CLS>
 __global__ void __launch_bounds__(256)
     eval_persistent_kernel(const uint64_t *boards, const int *order, const int *start,
                            unsigned long long *counter, uint4 *out, uint4 *gl, DevTables T)
@@ -1058,37 +1093,42 @@ __global__ void __launch_bounds__(256)
     extern __shared__ uint4 lds[];
     __shared__ long long s_item;
     __shared__ int s_slots[4][2][10];
-    const int nvalid = start[11];
-    const int big = start[8];                    // roots with 9..10 empty cells: [0, big)
-    const int nwg = start[kWaveMaxEmpties];      // roots with > kWaveMaxEmpties: [0, nwg)
-    uint4 *mine = gl + (size_t)blockIdx.x * 2 * 4 * kDagGlobalLayer;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = (long long)atomicAdd(&counter[0], 1ull);
-        __syncthreads();
-        const long long item = s_item;
-        __syncthreads();
-        if (item >= nwg) break;
-        const int root = order[item];
-        const RootInfo R = decode_root(boards[root]);
-        if (item < big)
-            solve_root<256>(R, T, mine, mine + 4 * kDagGlobalLayer, out + 4 * (size_t)root,
-                            s_slots[0][0], s_slots[0][1]);
-        else
-            solve_root<256>(R, T, lds, lds + 4 * T.dag_max[R.e], out + 4 * (size_t)root,
-                            s_slots[0][0], s_slots[0][1]);
-        __syncthreads();
-    }
-    const int w = threadIdx.x >> 6;
-    uint4 *wb = lds + (size_t)w * (kWaveLdsBytes / 16);
-    for (;;) {
-        unsigned long long got = 0;
-        if ((threadIdx.x & 63) == 0) got = atomicAdd(&counter[1], 1ull);
-        const long long item = nwg + (long long)__shfl(got, 0, 64);
-        if (item >= nvalid) break;
-        const int root = order[item];
-        const RootInfo R = decode_root(boards[root]);
-        solve_root<64>(R, T, wb, wb + 4 * 90, out + 4 * (size_t)root, s_slots[w][0], s_slots[w][1]);
-        wave_sync();
+    // bins are ordered by empty cells, most first: e occupies [start[e], start[e - 1])
+    const int lo = CLS == 0 ? 0 : CLS == 1 ? start[7] : start[kWaveMaxEmpties];
+    const int hi = CLS == 0 ? start[7] : CLS == 1 ? start[kWaveMaxEmpties] : start[11];
+    if (CLS < 2) {
+        const int big = start[8];  // roots with 9 or 10 empty cells: [0, big)
+        uint4 *mine = gl + (size_t)blockIdx.x * 2 * 4 * kDagGlobalLayer;
+        for (;;) {
+            if (threadIdx.x == 0) s_item = (long long)atomicAdd(&counter[CLS], 1ull);
+            __syncthreads();
+            const long long item = lo + s_item;
+            __syncthreads();
+            if (item >= hi) break;
+            const int root = order[item];
+            const RootInfo R = decode_root(boards[root]);
+            if (CLS == 0 && item < big)
+                solve_root<256>(R, T, mine, mine + 4 * kDagGlobalLayer, lds, out + 4 * (size_t)root,
+                                s_slots[0][0], s_slots[0][1]);
+            else
+                solve_root<256>(R, T, lds, lds + 4 * T.dag_max[R.e], lds + 8 * T.dag_max[R.e],
+                                out + 4 * (size_t)root, s_slots[0][0], s_slots[0][1]);
+            __syncthreads();
+        }
+    } else {
+        const int w = threadIdx.x >> 6;
+        uint4 *wb = lds + (size_t)w * (kWaveLdsBytes / 16);
+        for (;;) {
+            unsigned long long got = 0;
+            if ((threadIdx.x & 63) == 0) got = atomicAdd(&counter[2], 1ull);
+            const long long item = lo + (long long)__shfl(got, 0, 64);
+            if (item >= hi) break;
+            const int root = order[item];
+            const RootInfo R = decode_root(boards[root]);
+            solve_root<64>(R, T, wb, wb + 4 * 90, wb + 8 * 90, out + 4 * (size_t)root, s_slots[w][0],
+                           s_slots[w][1]);
+            wave_sync();
+        }
     }
 }
 
@@ -1105,11 +1145,11 @@ __global__ void __launch_bounds__(256)
         const int root = order[first + item];
         const RootInfo R = decode_root(boards[root]);
         if (use_global)
-            solve_root<256>(R, T, mine, mine + 4 * kDagGlobalLayer, out + 4 * (size_t)root,
+            solve_root<256>(R, T, mine, mine + 4 * kDagGlobalLayer, lds, out + 4 * (size_t)root,
                             s_slots[0], s_slots[1]);
         else
-            solve_root<256>(R, T, lds, lds + 4 * T.dag_max[R.e], out + 4 * (size_t)root,
-                            s_slots[0], s_slots[1]);
+            solve_root<256>(R, T, lds, lds + 4 * T.dag_max[R.e], lds + 8 * T.dag_max[R.e],
+                            out + 4 * (size_t)root, s_slots[0], s_slots[1]);
         __syncthreads();
     }
 }
@@ -1171,6 +1211,14 @@ hipError_t launch_eval_bin(const uint64_t *boards, size_t n, const EvalScratch &
     return hipGetLastError();
 }
 
+// Dynamic LDS of each persistent class.
+static int eval_class_lds_bytes(int cls)
+{
+    if (cls == 0) return std::max(dag_lds_bytes(8), std::max(dag_ftab_bytes(9), dag_ftab_bytes(10)));
+    if (cls == 1) return dag_lds_bytes(7);
+    return 4 * kWaveLdsBytes;
+}
+
 // Dynamic LDS above 64 KiB has to be granted per kernel.
 static hipError_t allow_lds(const void *kernel, int bytes)
 {
@@ -1183,11 +1231,34 @@ hipError_t launch_eval_persistent(const uint64_t *boards, size_t n, uint4 *out,
                                   hipStream_t s)
 {
     (void)n;
-    hipError_t e = allow_lds((const void *)eval_persistent_kernel, dag_lds_bytes(8));
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, S.counter, 2);
-    hipLaunchKernelGGL(eval_persistent_kernel, dim3(grid), dim3(256), dag_lds_bytes(8), s, boards,
-                       S.order, S.start, S.counter, out, S.global_layers, T);
+    const void *kern[3] = {(const void *)eval_persistent_kernel<0>, (const void *)eval_persistent_kernel<1>,
+                           (const void *)eval_persistent_kernel<2>};
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, S.counter, 3);
+    for (int c = 0; c < 3; c++) {
+        const int lds = eval_class_lds_bytes(c);
+        e = allow_lds(kern[c], lds);
+        if (e != hipSuccess) return e;
+        // class 0 owns the global layer slots: one per workgroup of `grid`
+        int g = grid;
+        if (c > 0) {
+            int per = 0;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern[c], 256, lds);
+            if (e != hipSuccess) return e;
+            g = std::max(1, per) * cus;
+        }
+        switch (c) {
+        case 0: hipLaunchKernelGGL(eval_persistent_kernel<0>, dim3(g), dim3(256), lds, s, boards, S.order,
+                                   S.start, S.counter, out, S.global_layers, T); break;
+        case 1: hipLaunchKernelGGL(eval_persistent_kernel<1>, dim3(g), dim3(256), lds, s, boards, S.order,
+                                   S.start, S.counter, out, S.global_layers, T); break;
+        default: hipLaunchKernelGGL(eval_persistent_kernel<2>, dim3(g), dim3(256), lds, s, boards, S.order,
+                                    S.start, S.counter, out, S.global_layers, T); break;
+        }
+    }
     return hipGetLastError();
 }
 
@@ -1197,9 +1268,10 @@ hipError_t launch_eval_group(const uint64_t *boards, int e, int first, int count
     if (count <= 0) return hipSuccess;
     const bool global = e > 8;
     const int grid = global ? std::min(count, S.global_slots) : count;
-    const hipError_t err = allow_lds((const void *)eval_group_kernel, global ? 0 : dag_lds_bytes(e));
+    const int lds = global ? dag_ftab_bytes(e) : dag_lds_bytes(e);
+    const hipError_t err = allow_lds((const void *)eval_group_kernel, lds);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(eval_group_kernel, dim3(grid), dim3(256), global ? 0 : dag_lds_bytes(e), s,
+    hipLaunchKernelGGL(eval_group_kernel, dim3(grid), dim3(256), lds, s,
                        boards, S.order, first, count, out, S.global_layers, global ? 1 : 0, T);
     return hipGetLastError();
 }

@@ -263,6 +263,20 @@ static void build_dag(DagLayout &L, int e)
         L.max_layer = std::max(L.max_layer, (int)L.node.size() - L.layer_start[t]);
     }
     L.layer_start[e + 1] = (int)L.node.size();
+    L.sub_mask.clear();
+    L.sub_rank.assign(1u << e, 0);
+    L.sub_start.assign(e + 2, 0);
+    L.max_subsets = 0;
+    for (int sz = 0; sz <= e; sz++) {
+        L.sub_start[sz] = (int)L.sub_mask.size();
+        for (unsigned m = 0; m < (1u << e); m++)
+            if (popcount9(m) == sz) {
+                L.sub_rank[m] = (uint16_t)(L.sub_mask.size() - L.sub_start[sz]);
+                L.sub_mask.push_back((uint16_t)m);
+            }
+        L.max_subsets = std::max(L.max_subsets, (int)L.sub_mask.size() - L.sub_start[sz]);
+    }
+    L.sub_start[e + 1] = (int)L.sub_mask.size();
 }
 
 const DagLayout &dag_layout(int e)

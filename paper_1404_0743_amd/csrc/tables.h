@@ -60,6 +60,12 @@ struct DagLayout {
     std::vector<uint32_t> node;     // cmask | omask << 16, layer by layer
     std::vector<uint16_t> rank;     // 3^e entries
     int max_layer;
+    // subsets of the e slots by size: sub_mask lists the masks of size 0,
+    // then size 1, ... (increasing within a size), sub_start[s] where size s
+    // starts (e + 2 entries); sub_rank[mask] = its index within its size
+    std::vector<uint16_t> sub_mask, sub_rank;
+    std::vector<int> sub_start;
+    int max_subsets;                // largest C(e, s)
 };
 
 const DagLayout &dag_layout(int e);
