@@ -1,0 +1,120 @@
+// device_common.h -- device helpers shared by the sweep and the endgame
+// kernels: the blocked offset of Section IV, superinfo loads and stores, the
+// five-set of a board from its quadrants' LineMasks.
+//
+// Data layout in HBM: a section table is entries x 64 B superinfos (win
+// words then not-lose words) in the 8^4-blocked order of Section IV.  One
+// lane owns one entry and keeps each 256-bit set in eight VGPRs, so every
+// set operation is plain per-lane integer work; nothing here is a dense
+// contraction, so there is no MFMA.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace pg {
+
+static __constant__ uint32_t c_pow3[10] = {1, 3, 9, 27, 81, 243, 729, 2187, 6561, 19683};
+
+// Entry offset in the 8^4-blocked layout (see pentago_section_offset).  The
+// host rejects sections of 2^32 entries or more, so 32-bit arithmetic holds.
+__device__ __forceinline__ uint32_t block_offset(const int *m, const int *idx)
+{
+    uint32_t B[4], r[4], s[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        B[j] = (uint32_t)idx[j] >> 3;
+        r[j] = (uint32_t)idx[j] & 7u;
+        s[j] = min(8u, (uint32_t)m[j] - 8u * B[j]);
+    }
+    const uint32_t m23 = (uint32_t)m[2] * (uint32_t)m[3];
+    uint32_t off = 8u * B[0] * (uint32_t)m[1] * m23;
+    off += s[0] * 8u * B[1] * m23;
+    off += s[0] * s[1] * 8u * B[2] * (uint32_t)m[3];
+    off += s[0] * s[1] * s[2] * 8u * B[3];
+    off += ((r[0] * s[1] + r[1]) * s[2] + r[2]) * s[3] + r[3];
+    return off;
+}
+
+// block_offset along a line of dimension D: with every index but idx[D]
+// fixed, the offset is c0 + c1 * B + c2 * s + c3 * r for B = idx[D] >> 3,
+// r = idx[D] & 7 and s = min(8, m[D] - 8 B) (the extent of that block).
+template <int D>
+__device__ __forceinline__ uint4 line_offset_coeffs(const int *m, const int *idx)
+{
+    uint32_t B[4], r[4], s[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        B[j] = (uint32_t)idx[j] >> 3;
+        r[j] = (uint32_t)idx[j] & 7u;
+        s[j] = min(8u, (uint32_t)m[j] - 8u * B[j]);
+    }
+    uint32_t c0 = 0, c1 = 8, c2 = 0, c3 = 1;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        uint32_t lo = 1, lo_d = 1, hi_m = 1, hi_s = 1, hi_s_d = 1;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            if (i < j) { lo *= s[i]; if (i != D) lo_d *= s[i]; }
+            if (i > j) { hi_m *= (uint32_t)m[i]; hi_s *= s[i]; if (i != D) hi_s_d *= s[i]; }
+        }
+        if (j < D) {
+            c0 += lo * 8u * B[j] * hi_m;   // whole blocks before, in dimensions < D
+            c2 += r[j] * hi_s_d;           // in-block index terms that carry s_D
+        } else if (j == D) {
+            c1 = lo * 8u * hi_m;
+            c3 = hi_s;
+        } else {
+            c2 += lo_d * 8u * B[j] * hi_m;  // whole blocks in dimensions > D carry s_D
+            c0 += r[j] * hi_s;
+        }
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ void load_info(const uint4 *p, Set256 &W, Set256 &N)
+{
+    const uint4 a = p[0], b = p[1], c = p[2], d = p[3];
+    W.w[0] = a.x; W.w[1] = a.y; W.w[2] = a.z; W.w[3] = a.w;
+    W.w[4] = b.x; W.w[5] = b.y; W.w[6] = b.z; W.w[7] = b.w;
+    N.w[0] = c.x; N.w[1] = c.y; N.w[2] = c.z; N.w[3] = c.w;
+    N.w[4] = d.x; N.w[5] = d.y; N.w[6] = d.z; N.w[7] = d.w;
+}
+
+__device__ __forceinline__ void store_info(uint4 *p, const Set256 &W, const Set256 &N)
+{
+    p[0] = make_uint4(W.w[0], W.w[1], W.w[2], W.w[3]);
+    p[1] = make_uint4(W.w[4], W.w[5], W.w[6], W.w[7]);
+    p[2] = make_uint4(N.w[0], N.w[1], N.w[2], N.w[3]);
+    p[3] = make_uint4(N.w[4], N.w[5], N.w[6], N.w[7]);
+}
+
+__device__ __forceinline__ Set256 board_five(const DevTables &T, const unsigned xm[4])
+{
+    const LineMasks l0 = T.lm[0 * 512 + xm[0]];
+    const LineMasks l1 = T.lm[1 * 512 + xm[1]];
+    const LineMasks l2 = T.lm[2 * 512 + xm[2]];
+    const LineMasks l3 = T.lm[3 * 512 + xm[3]];
+    return five_set(l0, l1, l2, l3);
+}
+
+
+__device__ __forceinline__ Set256 set_from(const uint4 *p)
+{
+    Set256 x;
+    const uint4 u = p[0], v = p[1];
+    x.w[0] = u.x; x.w[1] = u.y; x.w[2] = u.z; x.w[3] = u.w;
+    x.w[4] = v.x; x.w[5] = v.y; x.w[6] = v.z; x.w[7] = v.w;
+    return x;
+}
+
+// Clear n work-queue counters (a kernel, not a memset, so the sequence can
+// be captured in a graph).
+static __global__ void zero_counter_kernel(unsigned long long *c, int n)
+{
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+}
+
+}  // namespace pg

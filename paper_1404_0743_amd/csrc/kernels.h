@@ -55,7 +55,7 @@ struct SweepJob {
     int threads;       // workgroup size of the one-section sweep (256 or 512)
 };
 
-// Host launchers (kernels.hip).
+// Host launchers (sweep.hip, endgame.hip).
 hipError_t launch_sweep(const SweepJob &job, const DevTables &T, hipStream_t s);
 // Prepare the A/B child terms of dimension j (j in emask, j != d).
 hipError_t launch_prep(const SweepJob &job, int j, const DevTables &T, hipStream_t s);

@@ -1,102 +1,9 @@
-// kernels.hip -- HIP kernels for gfx950: the section sweep (Sections II-IV)
-// and the endgame DAG solver (Section VIII).
-//
-// Data layout in HBM: a section table is entries x 64 B superinfos (win
-// words then not-lose words) in the 8^4-blocked order of Section IV.  One
-// lane owns one entry and keeps each 256-bit set in eight VGPRs, so every
-// set operation is plain per-lane integer work; nothing here is a dense
-// contraction, so there is no MFMA.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-
-#include "kernels.h"
+// sweep.hip -- the section sweep (Sections II-IV, Fig. 3): one tile of G
+// lines along the quadrant that receives stones per workgroup, the child
+// prep pass for the other quadrants, and the batched persistent form.
+#include "device_common.h"
 
 namespace pg {
-
-__constant__ uint32_t c_pow3[10] = {1, 3, 9, 27, 81, 243, 729, 2187, 6561, 19683};
-
-// Entry offset in the 8^4-blocked layout (see pentago_section_offset).  The
-// host rejects sections of 2^32 entries or more, so 32-bit arithmetic holds.
-__device__ __forceinline__ uint32_t block_offset(const int *m, const int *idx)
-{
-    uint32_t B[4], r[4], s[4];
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        B[j] = (uint32_t)idx[j] >> 3;
-        r[j] = (uint32_t)idx[j] & 7u;
-        s[j] = min(8u, (uint32_t)m[j] - 8u * B[j]);
-    }
-    const uint32_t m23 = (uint32_t)m[2] * (uint32_t)m[3];
-    uint32_t off = 8u * B[0] * (uint32_t)m[1] * m23;
-    off += s[0] * 8u * B[1] * m23;
-    off += s[0] * s[1] * 8u * B[2] * (uint32_t)m[3];
-    off += s[0] * s[1] * s[2] * 8u * B[3];
-    off += ((r[0] * s[1] + r[1]) * s[2] + r[2]) * s[3] + r[3];
-    return off;
-}
-
-// block_offset along a line of dimension D: with every index but idx[D]
-// fixed, the offset is c0 + c1 * B + c2 * s + c3 * r for B = idx[D] >> 3,
-// r = idx[D] & 7 and s = min(8, m[D] - 8 B) (the extent of that block).
-template <int D>
-__device__ __forceinline__ uint4 line_offset_coeffs(const int *m, const int *idx)
-{
-    uint32_t B[4], r[4], s[4];
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        B[j] = (uint32_t)idx[j] >> 3;
-        r[j] = (uint32_t)idx[j] & 7u;
-        s[j] = min(8u, (uint32_t)m[j] - 8u * B[j]);
-    }
-    uint32_t c0 = 0, c1 = 8, c2 = 0, c3 = 1;
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        uint32_t lo = 1, lo_d = 1, hi_m = 1, hi_s = 1, hi_s_d = 1;
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            if (i < j) { lo *= s[i]; if (i != D) lo_d *= s[i]; }
-            if (i > j) { hi_m *= (uint32_t)m[i]; hi_s *= s[i]; if (i != D) hi_s_d *= s[i]; }
-        }
-        if (j < D) {
-            c0 += lo * 8u * B[j] * hi_m;   // whole blocks before, in dimensions < D
-            c2 += r[j] * hi_s_d;           // in-block index terms that carry s_D
-        } else if (j == D) {
-            c1 = lo * 8u * hi_m;
-            c3 = hi_s;
-        } else {
-            c2 += lo_d * 8u * B[j] * hi_m;  // whole blocks in dimensions > D carry s_D
-            c0 += r[j] * hi_s;
-        }
-    }
-    return make_uint4(c0, c1, c2, c3);
-}
-
-__device__ __forceinline__ void load_info(const uint4 *p, Set256 &W, Set256 &N)
-{
-    const uint4 a = p[0], b = p[1], c = p[2], d = p[3];
-    W.w[0] = a.x; W.w[1] = a.y; W.w[2] = a.z; W.w[3] = a.w;
-    W.w[4] = b.x; W.w[5] = b.y; W.w[6] = b.z; W.w[7] = b.w;
-    N.w[0] = c.x; N.w[1] = c.y; N.w[2] = c.z; N.w[3] = c.w;
-    N.w[4] = d.x; N.w[5] = d.y; N.w[6] = d.z; N.w[7] = d.w;
-}
-
-__device__ __forceinline__ void store_info(uint4 *p, const Set256 &W, const Set256 &N)
-{
-    p[0] = make_uint4(W.w[0], W.w[1], W.w[2], W.w[3]);
-    p[1] = make_uint4(W.w[4], W.w[5], W.w[6], W.w[7]);
-    p[2] = make_uint4(N.w[0], N.w[1], N.w[2], N.w[3]);
-    p[3] = make_uint4(N.w[4], N.w[5], N.w[6], N.w[7]);
-}
-
-__device__ __forceinline__ Set256 board_five(const DevTables &T, const unsigned xm[4])
-{
-    const LineMasks l0 = T.lm[0 * 512 + xm[0]];
-    const LineMasks l1 = T.lm[1 * 512 + xm[1]];
-    const LineMasks l2 = T.lm[2 * 512 + xm[2]];
-    const LineMasks l3 = T.lm[3 * 512 + xm[3]];
-    return five_set(l0, l1, l2, l3);
-}
 
 // ---------------------------------------------------------------------------
 // Section sweep
@@ -163,14 +70,6 @@ __device__ __forceinline__ void child_entry_terms(const SweepJob &J, const DevTa
     child_terms(Fc, W, N, A, B);
 }
 
-__device__ __forceinline__ Set256 set_from(const uint4 *p)
-{
-    Set256 x;
-    const uint4 u = p[0], v = p[1];
-    x.w[0] = u.x; x.w[1] = u.y; x.w[2] = u.z; x.w[3] = u.w;
-    x.w[4] = v.x; x.w[5] = v.y; x.w[6] = v.z; x.w[7] = v.w;
-    return x;
-}
 
 // ---------------------------------------------------------------------------
 // Five-in-a-row sets along a line (Section III five-sets, Section IV lines).
@@ -745,10 +644,6 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-__global__ void zero_counter_kernel(unsigned long long *c, int n)
-{
-    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
-}
 
 hipError_t launch_prep(const SweepJob &job, int j, const DevTables &T, hipStream_t s)
 {
@@ -816,463 +711,6 @@ hipError_t launch_sweep_batch(const SweepJob *dev_jobs, const long long *dev_til
     hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, dev_counter, 1);
     hipLaunchKernelGGL(sweep_batch_kernel, dim3(grid), dim3(256), lds_bytes, s, dev_jobs,
                        dev_tile_start, njobs, total_tiles, dev_counter, T);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Endgame DAG (Section VIII: the serial solver for boards beyond the
-// database, rotations folded in by rmax only, no canonicalisation).
-//
-// For a root with e empty cells, node (t, cmask, omask) is the root with t
-// more stones: the side to move at the root on the cells of cmask, the other
-// side on omask.  Layers are solved from t = e (full board) down to t = 0.
-// Each node keeps, for its parents, A = F_parent(node) | rmax(not N) and
-// B = F_parent(node) | rmax(not W) (64 B) in a layer buffer.
-// ---------------------------------------------------------------------------
-
-// Per root: two layers of node records (64 B each), then the layer's
-// five-set tables (two colours x the largest C(e, s) subsets, 32 B each).
-int dag_ftab_bytes(int e) { return 2 * dag_layout(e).max_subsets * 32; }
-
-int dag_lds_bytes(int e)
-{
-    return 2 * dag_layout(e).max_layer * 64 + dag_ftab_bytes(e);
-}
-
-struct RootInfo {
-    unsigned bm[4], wm[4];
-    int code[4];
-    int e;
-    int mover;
-    bool valid;
-};
-
-__device__ __forceinline__ RootInfo decode_root(uint64_t packed)
-{
-    RootInfo r;
-    int nb = 0, nw = 0;
-    r.valid = true;
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        int code = (int)((packed >> (16 * j)) & 0xffff);
-        r.code[j] = code;
-        if (code >= 19683) { r.valid = false; code = 0; }
-        unsigned bm = 0, wm = 0;
-        int x = code;
-        for (int l = 0; l < 9; l++) {
-            const int dgt = x % 3;
-            x /= 3;
-            bm |= (unsigned)(dgt == 1) << l;
-            wm |= (unsigned)(dgt == 2) << l;
-        }
-        r.bm[j] = bm;
-        r.wm[j] = wm;
-        nb += __popc(bm);
-        nw += __popc(wm);
-    }
-    r.e = 36 - nb - nw;
-    if (nb != nw && nb != nw + 1) r.valid = false;
-    if (r.e > 10) r.valid = false;
-    r.mover = nb == nw ? 1 : 2;
-    return r;
-}
-
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Solve one root with a group of GROUP threads: the whole workgroup (256) or
-// one wave (64).  `buf0` and `buf1` hold two layers of A/B records (64 B per
-// node); `ftab` the five-set tables of the current layer; slot_q/slot_l (10
-// ints each, LDS) the root's empty cells.
-//
-// Five-sets: the nodes of layer t hold ceil(t/2) stones of the root's mover
-// and floor(t/2) of the other side in the root's empty cells, and a colour's
-// five-set depends only on which cells hold that colour.  So each layer first
-// computes the five-set of every subset of the empty cells of those two sizes
-// (C(e, s) boards per colour instead of one per node and colour: 581 boards
-// against 4246 for 8 empty cells), and each node reads its two.
-template <int GROUP>
-__device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, uint4 *buf1,
-                           uint4 *ftab, uint4 *out, int *s_slot_q, int *s_slot_l)
-{
-    const int lane = GROUP == 256 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
-    if (lane == 0) {
-        int n = 0;
-        for (int j = 0; j < 4; j++) {
-            const unsigned empt = ~(R.bm[j] | R.wm[j]) & 0x1ffu;
-            for (int l = 0; l < 9; l++)
-                if ((empt >> l) & 1) {
-                    s_slot_q[n] = j;
-                    s_slot_l[n] = l;
-                    n++;
-                }
-        }
-    }
-    if (GROUP == 256) __syncthreads();
-    else wave_sync();
-    const int e = R.e;
-    const uint32_t *nodes = T.dag_node + T.dag_node_off[e];
-    const uint16_t *rank = T.dag_rank + T.dag_rank_off[e];
-    const uint16_t *smask = T.dag_sub_mask + T.dag_sub_off[e];
-    const uint16_t *srank = T.dag_sub_rank + T.dag_sub_off[e];
-    const int *layer = T.dag_layer[e];
-    const int smax = T.dag_sub_max[e];
-    // the root mover's stones and the other side's, per quadrant
-    unsigned cm0[4], om0[4];
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        cm0[j] = R.mover == 1 ? R.bm[j] : R.wm[j];
-        om0[j] = R.mover == 1 ? R.wm[j] : R.bm[j];
-    }
-    uint4 *cur = buf0, *prev = buf1;
-    for (int t = e; t >= 0; t--) {
-        const int n0 = layer[t], n1 = layer[t + 1];
-        const int x = (t & 1) ? 3 - R.mover : R.mover;   // side to move at layer t
-        const int xdigit = (t & 1) ? 2 : 1;              // slot digit of x's stones
-        // five-set tables of the layer: entries [0, nc) for the root mover's
-        // subsets of size ceil(t/2), [smax, smax + no) for the other side's
-        const int sc = (t + 1) >> 1, so = t >> 1;
-        const int nc = T.dag_sub_start[e][sc + 1] - T.dag_sub_start[e][sc];
-        const int no = T.dag_sub_start[e][so + 1] - T.dag_sub_start[e][so];
-        for (int i = lane; i < nc + no; i += GROUP) {
-            const bool mine = i < nc;
-            const int r = mine ? i : i - nc;
-            const unsigned m = smask[T.dag_sub_start[e][mine ? sc : so] + r];
-            unsigned xm[4] = {mine ? cm0[0] : om0[0], mine ? cm0[1] : om0[1], mine ? cm0[2] : om0[2],
-                              mine ? cm0[3] : om0[3]};
-            for (int sl = 0; sl < e; sl++)
-                if ((m >> sl) & 1) {
-                    const int q = s_slot_q[sl];
-                    const unsigned bit = 1u << s_slot_l[sl];
-                    xm[0] |= q == 0 ? bit : 0u;
-                    xm[1] |= q == 1 ? bit : 0u;
-                    xm[2] |= q == 2 ? bit : 0u;
-                    xm[3] |= q == 3 ? bit : 0u;
-                }
-            const Set256 F = board_five(T, xm);
-            uint4 *dst = ftab + 2 * ((mine ? 0 : smax) + r);
-            dst[0] = make_uint4(F.w[0], F.w[1], F.w[2], F.w[3]);
-            dst[1] = make_uint4(F.w[4], F.w[5], F.w[6], F.w[7]);
-        }
-        if (GROUP == 256) __syncthreads();
-        else wave_sync();
-        for (int i = n0 + lane; i < n1; i += GROUP) {
-            const uint32_t nd = nodes[i];
-            const unsigned cmask = nd & 0xffffu, omask = nd >> 16;
-            int code = 0;
-            for (int sl = e - 1; sl >= 0; sl--)
-                code = 3 * code + (((cmask >> sl) & 1) ? 1 : ((omask >> sl) & 1) ? 2 : 0);
-            const Set256 Fc = set_from(ftab + 2 * srank[cmask]);
-            const Set256 Fo = set_from(ftab + 2 * (smax + srank[omask]));
-            const Set256 &Fx = x == R.mover ? Fc : Fo;
-            const Set256 &Fy = x == R.mover ? Fo : Fc;
-            Set256 Wnt = s_zero(), Nnt = s_zero();
-            if (t == e) {
-                Nnt = s_full();
-            } else {
-                const unsigned free = ~(cmask | omask) & ((1u << e) - 1u);
-                unsigned f = free;
-                while (f) {
-                    const int sl = __builtin_ctz(f);
-                    f &= f - 1;
-                    const int ci = rank[code + xdigit * (int)c_pow3[sl]];
-                    const uint4 *p = prev + 4 * ci;
-                    s_or_into(Wnt, set_from(p));
-                    s_or_into(Nnt, set_from(p + 2));
-                }
-            }
-            Set256 W, N;
-            combine(Fx, Fy, Wnt, Nnt, W, N);
-            if (t == 0) {
-                store_info(out, W, N);
-            } else {
-                Set256 A, B;
-                child_terms(Fy, W, N, A, B);
-                uint4 *p = cur + 4 * (i - n0);
-                p[0] = make_uint4(A.w[0], A.w[1], A.w[2], A.w[3]);
-                p[1] = make_uint4(A.w[4], A.w[5], A.w[6], A.w[7]);
-                p[2] = make_uint4(B.w[0], B.w[1], B.w[2], B.w[3]);
-                p[3] = make_uint4(B.w[4], B.w[5], B.w[6], B.w[7]);
-            }
-        }
-        if (GROUP == 256) __syncthreads();
-        else wave_sync();
-        uint4 *tmp = cur;
-        cur = prev;
-        prev = tmp;
-    }
-}
-
-// Count roots per number of empty cells (index 11: invalid boards).  Counts
-// are gathered per workgroup in LDS first, so each workgroup adds to the
-// global counters once per bin (a million lanes adding to twelve global
-// counters directly serialise on them).
-__global__ void __launch_bounds__(256)
-    eval_count_kernel(const uint64_t *boards, size_t n, int *count, uint8_t *empties, int *status,
-                      uint4 *out)
-{
-    __shared__ int lc[12];
-    if (threadIdx.x < 12) lc[threadIdx.x] = 0;
-    __syncthreads();
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        const RootInfo R = decode_root(boards[i]);
-        const int e = R.valid ? R.e : 11;
-        empties[i] = (uint8_t)e;
-        atomicAdd(&lc[e], 1);
-        if (!R.valid) {
-            const uint4 z = make_uint4(0, 0, 0, 0);
-            out[4 * i] = z; out[4 * i + 1] = z; out[4 * i + 2] = z; out[4 * i + 3] = z;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < 12 && lc[threadIdx.x]) {
-        atomicAdd(&count[threadIdx.x], lc[threadIdx.x]);
-        if (threadIdx.x == 11 && status) atomicAdd(status, lc[11]);
-    }
-}
-
-// Bucket starts, most empty cells first.
-__global__ void eval_scan_kernel(const int *count, int *start, int *cursor)
-{
-    if (threadIdx.x != 0) return;
-    int acc = 0;
-    for (int e = 10; e >= 0; e--) {
-        start[e] = acc;
-        cursor[e] = 0;
-        acc += count[e];
-    }
-    start[11] = acc;
-    cursor[11] = 0;
-}
-
-// Roots into their bins: positions inside the workgroup from LDS counters,
-// one global reservation per bin per workgroup.
-__global__ void __launch_bounds__(256)
-    eval_scatter_kernel(const uint8_t *empties, size_t n, const int *start, int *cursor, int *order)
-{
-    __shared__ int lc[11], base[11];
-    if (threadIdx.x < 11) lc[threadIdx.x] = 0;
-    __syncthreads();
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int e = i < n ? empties[i] : 11;
-    const int local = e <= 10 ? atomicAdd(&lc[e], 1) : 0;
-    __syncthreads();
-    if (threadIdx.x < 11 && lc[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], lc[threadIdx.x]);
-    __syncthreads();
-    if (e <= 10) order[start[e] + base[e] + local] = (int)i;
-}
-
-__global__ void zero_ints_kernel(int *p, int n)
-{
-    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
-}
-
-// Persistent solve over all valid roots, most empty cells first.  The roots
-// are binned by number of empty cells on the device; three persistent
-// launches follow one another on the stream, one per LDS class, each taking
-// roots from its own device work queue (no host synchronisation):
-//   class 0: 8 to 10 empty cells, a workgroup per root (9 and 10 keep their
-//            layers in the workgroup's slot of a global buffer);
-//   class 1: 7 empty cells, a workgroup per root, a smaller LDS footprint;
-//   class 2: up to kWaveMaxEmpties, one wave per root, four per workgroup,
-//            synchronised per wave only.
-constexpr int kWaveMaxEmpties = 6;
-// two layers of the widest 6-empty layer, then the five-set tables (C(6,3) = 20)
-constexpr int kWaveLdsBytes = 2 * 90 * 64 + 2 * 20 * 32;
-
-template <int CLS>
-__global__ void __launch_bounds__(256)
-    eval_persistent_kernel(const uint64_t *boards, const int *order, const int *start,
-                           unsigned long long *counter, uint4 *out, uint4 *gl, DevTables T)
-{
-    extern __shared__ uint4 lds[];
-    __shared__ long long s_item;
-    __shared__ int s_slots[4][2][10];
-    // bins are ordered by empty cells, most first: e occupies [start[e], start[e - 1])
-    const int lo = CLS == 0 ? 0 : CLS == 1 ? start[7] : start[kWaveMaxEmpties];
-    const int hi = CLS == 0 ? start[7] : CLS == 1 ? start[kWaveMaxEmpties] : start[11];
-    if (CLS < 2) {
-        const int big = start[8];  // roots with 9 or 10 empty cells: [0, big)
-        uint4 *mine = gl + (size_t)blockIdx.x * 2 * 4 * kDagGlobalLayer;
-        for (;;) {
-            if (threadIdx.x == 0) s_item = (long long)atomicAdd(&counter[CLS], 1ull);
-            __syncthreads();
-            const long long item = lo + s_item;
-            __syncthreads();
-            if (item >= hi) break;
-            const int root = order[item];
-            const RootInfo R = decode_root(boards[root]);
-            if (CLS == 0 && item < big)
-                solve_root<256>(R, T, mine, mine + 4 * kDagGlobalLayer, lds, out + 4 * (size_t)root,
-                                s_slots[0][0], s_slots[0][1]);
-            else
-                solve_root<256>(R, T, lds, lds + 4 * T.dag_max[R.e], lds + 8 * T.dag_max[R.e],
-                                out + 4 * (size_t)root, s_slots[0][0], s_slots[0][1]);
-            __syncthreads();
-        }
-    } else {
-        const int w = threadIdx.x >> 6;
-        uint4 *wb = lds + (size_t)w * (kWaveLdsBytes / 16);
-        for (;;) {
-            unsigned long long got = 0;
-            if ((threadIdx.x & 63) == 0) got = atomicAdd(&counter[2], 1ull);
-            const long long item = lo + (long long)__shfl(got, 0, 64);
-            if (item >= hi) break;
-            const int root = order[item];
-            const RootInfo R = decode_root(boards[root]);
-            solve_root<64>(R, T, wb, wb + 4 * 90, wb + 8 * 90, out + 4 * (size_t)root, s_slots[w][0],
-                           s_slots[w][1]);
-            wave_sync();
-        }
-    }
-}
-
-// Plain form: the roots of one empties group, one workgroup per root
-// (grid-stride when the group needs global layer buffers).
-__global__ void __launch_bounds__(256)
-    eval_group_kernel(const uint64_t *boards, const int *order, int first, int count, uint4 *out,
-                      uint4 *gl, int use_global, DevTables T)
-{
-    extern __shared__ uint4 lds[];
-    __shared__ int s_slots[2][10];
-    uint4 *mine = gl + (size_t)blockIdx.x * 2 * 4 * kDagGlobalLayer;
-    for (int item = blockIdx.x; item < count; item += gridDim.x) {
-        const int root = order[first + item];
-        const RootInfo R = decode_root(boards[root]);
-        if (use_global)
-            solve_root<256>(R, T, mine, mine + 4 * kDagGlobalLayer, lds, out + 4 * (size_t)root,
-                            s_slots[0], s_slots[1]);
-        else
-            solve_root<256>(R, T, lds, lds + 4 * T.dag_max[R.e], lds + 8 * T.dag_max[R.e],
-                            out + 4 * (size_t)root, s_slots[0], s_slots[1]);
-        __syncthreads();
-    }
-}
-
-// Resident-section lookup (Section VIII: positions inside the database are
-// read, not solved): each quadrant of the query is turned to its
-// rotation-minimal pattern (k_j turns), the entry is read and shifted back by
-// k_j along every dimension.
-__global__ void __launch_bounds__(256)
-    lookup_kernel(const uint64_t *boards, const int *sec_of, int n, const ResidentSection *secs,
-                  uint4 *out, DevTables T)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint64_t b = boards[i];
-    const ResidentSection S = secs[sec_of[i]];
-    int idx[4], k[4];
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        const uint16_t cc = T.canon[(b >> (16 * j)) & 0xffff];
-        idx[j] = cc & 0xfff;
-        k[j] = cc >> 12;
-    }
-    Set256 W, N;
-    load_info(S.table + 4 * block_offset(S.m, idx), W, N);
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        W = shift_dim(W, j, k[j]);
-        N = shift_dim(N, j, k[j]);
-    }
-    store_info(out + 4 * (size_t)i, W, N);
-}
-
-hipError_t launch_lookup(const uint64_t *boards, const int *sec_of, int n,
-                         const ResidentSection *secs, uint4 *out, const DevTables &T, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(lookup_kernel, dim3((n + 255) / 256), dim3(256), 0, s, boards, sec_of, n,
-                       secs, out, T);
-    return hipGetLastError();
-}
-
-hipError_t launch_eval_bin(const uint64_t *boards, size_t n, const EvalScratch &S, int *status,
-                           uint4 *out, const DevTables &T, hipStream_t s)
-{
-    (void)T;
-    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, S.count, 16);
-    if (n) {
-        const unsigned g = (unsigned)((n + 255) / 256);
-        hipLaunchKernelGGL(eval_count_kernel, dim3(g), dim3(256), 0, s, boards, n, S.count,
-                           S.empties, status, out);
-    }
-    hipLaunchKernelGGL(eval_scan_kernel, dim3(1), dim3(64), 0, s, S.count, S.start, S.cursor);
-    if (n) {
-        const unsigned g = (unsigned)((n + 255) / 256);
-        hipLaunchKernelGGL(eval_scatter_kernel, dim3(g), dim3(256), 0, s, S.empties, n, S.start,
-                           S.cursor, S.order);
-    }
-    return hipGetLastError();
-}
-
-// Dynamic LDS of each persistent class.
-static int eval_class_lds_bytes(int cls)
-{
-    if (cls == 0) return std::max(dag_lds_bytes(8), std::max(dag_ftab_bytes(9), dag_ftab_bytes(10)));
-    if (cls == 1) return dag_lds_bytes(7);
-    return 4 * kWaveLdsBytes;
-}
-
-// Dynamic LDS above 64 KiB has to be granted per kernel.
-static hipError_t allow_lds(const void *kernel, int bytes)
-{
-    if (bytes <= 65536) return hipSuccess;
-    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-}
-
-hipError_t launch_eval_persistent(const uint64_t *boards, size_t n, uint4 *out,
-                                  const EvalScratch &S, int grid, const DevTables &T,
-                                  hipStream_t s)
-{
-    (void)n;
-    int dev = 0, cus = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return e;
-    const void *kern[3] = {(const void *)eval_persistent_kernel<0>, (const void *)eval_persistent_kernel<1>,
-                           (const void *)eval_persistent_kernel<2>};
-    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, S.counter, 3);
-    for (int c = 0; c < 3; c++) {
-        const int lds = eval_class_lds_bytes(c);
-        e = allow_lds(kern[c], lds);
-        if (e != hipSuccess) return e;
-        // class 0 owns the global layer slots: one per workgroup of `grid`
-        int g = grid;
-        if (c > 0) {
-            int per = 0;
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern[c], 256, lds);
-            if (e != hipSuccess) return e;
-            g = std::max(1, per) * cus;
-        }
-        switch (c) {
-        case 0: hipLaunchKernelGGL(eval_persistent_kernel<0>, dim3(g), dim3(256), lds, s, boards, S.order,
-                                   S.start, S.counter, out, S.global_layers, T); break;
-        case 1: hipLaunchKernelGGL(eval_persistent_kernel<1>, dim3(g), dim3(256), lds, s, boards, S.order,
-                                   S.start, S.counter, out, S.global_layers, T); break;
-        default: hipLaunchKernelGGL(eval_persistent_kernel<2>, dim3(g), dim3(256), lds, s, boards, S.order,
-                                    S.start, S.counter, out, S.global_layers, T); break;
-        }
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_eval_group(const uint64_t *boards, int e, int first, int count, uint4 *out,
-                             const EvalScratch &S, const DevTables &T, hipStream_t s)
-{
-    if (count <= 0) return hipSuccess;
-    const bool global = e > 8;
-    const int grid = global ? std::min(count, S.global_slots) : count;
-    const int lds = global ? dag_ftab_bytes(e) : dag_lds_bytes(e);
-    const hipError_t err = allow_lds((const void *)eval_group_kernel, lds);
-    if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(eval_group_kernel, dim3(grid), dim3(256), lds, s,
-                       boards, S.order, first, count, out, S.global_layers, global ? 1 : 0, T);
     return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ struct HostTables {
     std::vector<uint16_t> turn1;  // per code: code after one counter-clockwise turn
     std::vector<LineMasks> lm;    // [quadrant * 512 + stone mask]
 
-    // Line structure used by the sweep (five_lut in kernels.hip):
+    // Line structure used by the sweep (five_lut in sweep.hip):
     // sel[(j * 512 + m) * 4 + k] describes the lines through quadrant j that
     // its stone mask m completes after k turns.  For each field f = a, b, c of
     // LineMasks the 6-bit set sigma_f (bit s iff nibble s of field f of
