@@ -20,18 +20,6 @@ __device__ __forceinline__ int get4(const Idx4 &x, int j)
     return j == 0 ? x.v[0] : j == 1 ? x.v[1] : j == 2 ? x.v[2] : x.v[3];
 }
 
-__device__ __forceinline__ void set4(Idx4 &x, int j, int val)
-{
-#pragma unroll
-    for (int i = 0; i < 4; i++)
-        if (i == j) x.v[i] = val;
-}
-
-__device__ __forceinline__ int mdim(const SweepJob &J, int j)
-{
-    return j == 0 ? J.m[0] : j == 1 ? J.m[1] : j == 2 ? J.m[2] : J.m[3];
-}
-
 // A child entry's contribution, prepared once per child entry of a staged
 // line and used by every parent of the line that reaches it (Section III:
 // rmax is translation invariant, so it commutes with the canonicalising
