@@ -124,6 +124,15 @@ int pentago_autotune_section(pentago_section s, const pentago_superinfo *const c
                              pentago_superinfo *out, void *hip_stream, int *tile_lines,
                              int *tile_threads, float *best_ms);
 
+/* pentago_solve_section with an explicit tile shape (for tuning and tests):
+ * tile_lines lines of the section per tile (1..8), tile_threads threads per
+ * workgroup (256 or 512).  ERANGE when the shape is outside those ranges or
+ * its tile needs more than 64 KiB of LDS; otherwise as pentago_solve_section
+ * (the result does not depend on the shape). */
+int pentago_solve_section_shape(pentago_section s, const pentago_superinfo *const child[4],
+                                pentago_superinfo *out, void *hip_stream, int tile_lines,
+                                int tile_threads);
+
 /* One section of a batch: its counts, its four child tables as for
  * pentago_solve_section, and its output. */
 typedef struct {

@@ -110,3 +110,19 @@ extern "C" int pentago_autotune_section(pentago_section s, const pentago_superin
     if (best_ms) *best_ms = best;
     return rc;
 }
+
+extern "C" int pentago_solve_section_shape(pentago_section s, const pentago_superinfo *const child[4],
+                                           pentago_superinfo *out, void *hip_stream, int tile_lines,
+                                           int tile_threads)
+{
+    if (tile_lines < 1 || tile_lines > 8 || (tile_threads != 256 && tile_threads != 512))
+        return fail(PENTAGO_ERANGE, "tile shape: 1..8 lines, 256 or 512 threads");
+    DevTables T;
+    int rc = device_tables(&T);
+    if (rc) return rc;
+    SweepJob J;
+    rc = make_job(s, child, out, &J, -1, tile_lines, tile_threads);
+    if (rc) return rc;
+    if (J.lds_bytes > 65536) return fail(PENTAGO_ERANGE, "tile shape needs more than 64 KiB of LDS");
+    return run_job(J, T, (hipStream_t)hip_stream);
+}

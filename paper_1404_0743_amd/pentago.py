@@ -64,6 +64,7 @@ _SIGS = {
     "pentago_solve_section": ([Section, _P, _P, _P], ctypes.c_int),
     "pentago_solve_sections": ([_P, ctypes.c_size_t, _P], ctypes.c_int),
     "pentago_autotune_section": ([Section, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "pentago_solve_section_shape": ([Section, _P, _P, _P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "pentago_plan_create": ([_P, ctypes.c_size_t, _P], ctypes.c_int),
     "pentago_plan_launch": ([_P, _P], ctypes.c_int),
     "pentago_plan_launch_graph": ([_P, _P], ctypes.c_int),
@@ -217,6 +218,14 @@ def pentago_autotune_section(counts, children, out, stream=None):
                                           ctypes.byref(g), ctypes.byref(nt), ctypes.byref(ms)),
            "pentago_autotune_section")
     return g.value, nt.value, ms.value
+
+
+def pentago_solve_section_shape(counts, children, out, tile_lines, tile_threads, stream=None):
+    """The sweep with an explicit tile shape (lines per tile, threads)."""
+    ch = (ctypes.c_void_p * 4)(*[None if c is None else c.data_ptr() for c in children])
+    _check(lib().pentago_solve_section_shape(section(counts), ch, _dev_ptr(out), _stream(stream),
+                                             int(tile_lines), int(tile_threads)),
+           "pentago_solve_section_shape")
 
 
 def _job_array(jobs):

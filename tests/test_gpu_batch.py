@@ -114,3 +114,39 @@ def test_autotuned_tiles_give_same_bytes(P):
     out2 = solve(P, counts, [None, None, None, ch])
     torch.cuda.synchronize()
     assert torch.equal(ref, out2)
+
+
+# sections whose staged quadrant (the one with most empty cells) is 2, 1, 0
+# and 3, with full-board children (35 stones) or children from the chain
+SHAPE_SECTIONS = [((7, 2), (2, 7), (1, 7), (8, 1)),
+                  ((9, 0), (0, 8), (3, 6), (6, 3)),
+                  ((8, 0), (2, 7), (2, 7), (6, 3)),
+                  ((5, 4), (4, 5), (5, 4), (4, 4)),
+                  ((7, 1), (2, 7), (1, 8), (7, 1)),
+                  ((7, 1), (1, 7), (2, 7), (7, 1))]
+
+
+@pytest.mark.parametrize("counts", SHAPE_SECTIONS, ids=str)
+def test_every_tile_shape_gives_same_bytes(P, counts):
+    log("tile shapes", counts)
+    cache = {}
+    ref, ch = chain(P, counts, cache)
+    torch.cuda.synchronize()
+    tried = 0
+    out = torch.empty_like(ref)
+    for threads in (256, 512):
+        for lines in range(1, 9):
+            out.fill_(-1)
+            try:
+                P.pentago_solve_section_shape(counts, ch, out, lines, threads)
+            except P.PentagoError as e:
+                assert e.code == P.ERANGE  # tile over 64 KiB of LDS
+                continue
+            torch.cuda.synchronize()
+            assert torch.equal(ref, out), (lines, threads)
+            tried += 1
+    assert tried >= 4
+    with pytest.raises(P.PentagoError):
+        P.pentago_solve_section_shape(counts, ch, out, 9, 256)
+    with pytest.raises(P.PentagoError):
+        P.pentago_solve_section_shape(counts, ch, out, 4, 128)
