@@ -317,6 +317,58 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// A batch whose roots all fall in one class (the server batches its searches
+// by empty cells): the roots are taken in order from one device queue, with
+// no binning pass.  Boards the class cannot hold get zero tables.
+template <int CLS>
+__global__ void __launch_bounds__(256)
+    eval_direct_kernel(const uint64_t *boards, int n, unsigned long long *counter, uint4 *out,
+                       uint4 *gl, DevTables T)
+{
+    extern __shared__ uint4 lds[];
+    __shared__ long long s_item;
+    __shared__ int s_slots[4][2][10];
+    if (CLS < 2) {
+        uint4 *mine = gl + (size_t)blockIdx.x * 2 * 4 * kDagGlobalLayer;
+        for (;;) {
+            if (threadIdx.x == 0) s_item = (long long)atomicAdd(counter, 1ull);
+            __syncthreads();
+            const long long item = s_item;
+            __syncthreads();
+            if (item >= n) break;
+            const RootInfo R = decode_root(boards[item]);
+            const bool ok = R.valid && (CLS == 0 ? (R.e >= 8 && (R.e == 8 || gl != nullptr)) : R.e == 7);
+            if (!ok) {
+                if (threadIdx.x < 4) out[4 * item + threadIdx.x] = make_uint4(0, 0, 0, 0);
+            } else if (CLS == 0 && R.e > 8) {
+                solve_root<256>(R, T, mine, mine + 4 * kDagGlobalLayer, lds, out + 4 * (size_t)item,
+                                s_slots[0][0], s_slots[0][1]);
+            } else {
+                solve_root<256>(R, T, lds, lds + 4 * T.dag_max[R.e], lds + 8 * T.dag_max[R.e],
+                                out + 4 * (size_t)item, s_slots[0][0], s_slots[0][1]);
+            }
+            __syncthreads();
+        }
+    } else {
+        const int w = threadIdx.x >> 6;
+        uint4 *wb = lds + (size_t)w * (kWaveLdsBytes / 16);
+        for (;;) {
+            unsigned long long got = 0;
+            if ((threadIdx.x & 63) == 0) got = atomicAdd(counter, 1ull);
+            const long long item = (long long)__shfl(got, 0, 64);
+            if (item >= n) break;
+            const RootInfo R = decode_root(boards[item]);
+            if (!R.valid || R.e > kWaveMaxEmpties) {
+                if ((threadIdx.x & 63) < 4) out[4 * item + (threadIdx.x & 3)] = make_uint4(0, 0, 0, 0);
+            } else {
+                solve_root<64>(R, T, wb, wb + 4 * 90, wb + 8 * 90, out + 4 * (size_t)item, s_slots[w][0],
+                               s_slots[w][1]);
+            }
+            wave_sync();
+        }
+    }
+}
+
 // Plain form: the roots of one empties group, one workgroup per root
 // (grid-stride when the group needs global layer buffers).
 __global__ void __launch_bounds__(256)
@@ -443,6 +495,41 @@ hipError_t launch_eval_persistent(const uint64_t *boards, size_t n, uint4 *out,
         default: hipLaunchKernelGGL(eval_persistent_kernel<2>, dim3(g), dim3(256), lds, s, boards, S.order,
                                     S.start, S.counter, out, S.global_layers, T); break;
         }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_direct(const uint64_t *boards, int n, uint4 *out, int cls,
+                              unsigned long long *counter, uint4 *global_layers, int grid,
+                              const DevTables &T, hipStream_t s)
+{
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const void *kern[3] = {(const void *)eval_direct_kernel<0>, (const void *)eval_direct_kernel<1>,
+                           (const void *)eval_direct_kernel<2>};
+    const int lds = eval_class_lds_bytes(cls);
+    e = allow_lds(kern[cls], lds);
+    if (e != hipSuccess) return e;
+    int g = grid;  // class 0 owns the global layer slots: one per workgroup of `grid`
+    if (cls > 0) {
+        int per = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern[cls], 256, lds);
+        if (e != hipSuccess) return e;
+        g = std::max(1, per) * cus;
+    }
+    // no more workgroups than the batch can use
+    g = std::min(g, cls == 2 ? (n + 3) / 4 : n);
+    if (g <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, counter, 1);
+    switch (cls) {
+    case 0: hipLaunchKernelGGL(eval_direct_kernel<0>, dim3(g), dim3(256), lds, s, boards, n, counter, out,
+                               global_layers, T); break;
+    case 1: hipLaunchKernelGGL(eval_direct_kernel<1>, dim3(g), dim3(256), lds, s, boards, n, counter, out,
+                               global_layers, T); break;
+    default: hipLaunchKernelGGL(eval_direct_kernel<2>, dim3(g), dim3(256), lds, s, boards, n, counter, out,
+                                global_layers, T); break;
     }
     return hipGetLastError();
 }

@@ -102,6 +102,27 @@ int eval_enqueue(const uint64_t *boards, size_t n, uint4 *out, int *status, bool
     return 0;
 }
 
+// Enqueue one batch whose roots all belong to endgame class cls (see
+// launch_eval_direct): one queue counter and, for roots with 9 or 10 empty
+// cells, the global layer slots; no binning.
+int eval_enqueue_class(const uint64_t *boards, size_t n, uint4 *out, int cls, bool deep, int grid,
+                       hipStream_t st)
+{
+    DevTables T;
+    int rc = device_tables(&T);
+    if (rc) return rc;
+    void *base = nullptr;
+    const size_t glayer = deep ? (size_t)grid * 2 * kDagGlobalLayer * 64 : 0;
+    hipError_t e = hipMallocAsync(&base, glayer + 256, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(eval scratch)");
+    uint4 *gl = deep ? (uint4 *)base : nullptr;
+    unsigned long long *counter = (unsigned long long *)((char *)base + glayer);
+    e = launch_eval_direct(boards, (int)n, out, cls, counter, gl, grid, T, st);
+    (void)hipFreeAsync(base, st);
+    if (e != hipSuccess) return hip_fail(e, "eval launch");
+    return 0;
+}
+
 }  // namespace pg
 
 using namespace pg;

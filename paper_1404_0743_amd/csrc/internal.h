@@ -34,5 +34,7 @@ int eval_grid(int *grid);
 size_t eval_scratch_bytes(size_t n, int grid, bool deep);
 int eval_enqueue(const uint64_t *boards, size_t n, uint4 *out, int *status, bool deep, int grid,
                  hipStream_t st);
+int eval_enqueue_class(const uint64_t *boards, size_t n, uint4 *out, int cls, bool deep, int grid,
+                       hipStream_t st);
 
 }  // namespace pg

@@ -87,6 +87,11 @@ hipError_t launch_eval_persistent(const uint64_t *boards, size_t n, uint4 *out,
 hipError_t launch_eval_group(const uint64_t *boards, int e, int first, int count, uint4 *out,
                              const EvalScratch &S, const DevTables &T, hipStream_t s);
 
+// One batch of roots of a single class (0: 8-10 empty cells, 9-10 needing
+// global_layers; 1: 7; 2: up to 6), taken in order, no binning.
+hipError_t launch_eval_direct(const uint64_t *boards, int n, uint4 *out, int cls,
+                              unsigned long long *counter, uint4 *global_layers, int grid,
+                              const DevTables &T, hipStream_t s);
 int dag_lds_bytes(int e);
 int dag_ftab_bytes(int e);
 

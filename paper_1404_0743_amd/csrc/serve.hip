@@ -136,7 +136,9 @@ int launch_batch(pentago_server *S, int si, Batch &B)
         if (e == hipSuccess)
             e = launch_lookup(S->d_boards[si], S->d_sec[si], (int)n, S->d_secs, S->d_out[si], S->T, st);
     } else if (e == hipSuccess) {
-        rc = eval_enqueue(S->d_boards[si], n, S->d_out[si], nullptr, B.cls == 4, S->grid, st);
+        // search classes 1..4 (empties <= 6, 7, 8, 9-10) -> endgame classes 2, 1, 0, 0
+        const int ecls = B.cls == 1 ? 2 : B.cls == 2 ? 1 : 0;
+        rc = eval_enqueue_class(S->d_boards[si], n, S->d_out[si], ecls, B.cls == 4, S->grid, st);
     }
     if (e == hipSuccess && rc == 0)
         e = hipMemcpyAsync(S->h_out[si], S->d_out[si], n * 64, hipMemcpyDeviceToHost, st);
