@@ -125,7 +125,7 @@ def main():
     terminal_ms = t0.elapsed_time(t1)
     children = [None, None, None, child]
     # tile shape picked by the library's autotuner (setup, not timed)
-    tile_lines, tile_threads, tune_ms = P.pentago_autotune_section(SECTION, children, out, stream)
+    tile, tune_ms = P.pentago_autotune_section(SECTION, children, out, stream)
 
     for _ in range(args.warmup):
         P.pentago_solve_section(SECTION, children, out, stream)
@@ -184,7 +184,7 @@ def main():
                                "white to move, %d entries, %d positions, child section "
                                "(5,4),(4,5),(5,4),(4,5) %d entries resident" % (entries, positions, centries),
                    "entries": entries, "positions": positions, "shape": list(shape),
-                   "tile_lines": tile_lines, "tile_threads": tile_threads},
+                   "tile_lines": tile["lines"], "tile_threads": tile["threads"], "tile_order": tile["order"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "kernel_ms": {"sweep_avg": avg_ms, "sweep_min": float(np.min(kernel_ms)),

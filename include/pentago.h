@@ -113,25 +113,33 @@ int pentago_child_section(pentago_section s, int j, pentago_section *child);
 int pentago_solve_section(pentago_section s, const pentago_superinfo *const child[4],
                           pentago_superinfo *out, void *hip_stream);
 
-/* The tile autotuner: times every tile shape the section admits (lines of
- * the section along the staged quadrant per tile, and workgroup size 256 or
- * 512) with HIP events on hip_stream, remembers the fastest for this section
- * geometry (later pentago_solve_section calls with the same geometry use it;
- * pentago_solve_sections uses its lines per tile) and leaves out holding the
- * sweep's result.  Synchronises the stream.  tile_lines, tile_threads and
- * best_ms may be NULL. */
-int pentago_autotune_section(pentago_section s, const pentago_superinfo *const child[4],
-                             pentago_superinfo *out, void *hip_stream, int *tile_lines,
-                             int *tile_threads, float *best_ms);
+/* Tile shape of the sweep: lines of the section along the staged quadrant
+ * per tile (1..8), threads per workgroup (256 or 512), and the order in
+ * which workgroups take tiles (0: tile = workgroup index; 1: each of the 8
+ * XCDs of the GPU, which receive workgroups in turn, takes a contiguous range
+ * of tiles). */
+typedef struct {
+    int32_t lines;
+    int32_t threads;
+    int32_t order;
+} pentago_tile_shape;
 
-/* pentago_solve_section with an explicit tile shape (for tuning and tests):
- * tile_lines lines of the section per tile (1..8), tile_threads threads per
- * workgroup (256 or 512).  ERANGE when the shape is outside those ranges or
- * its tile needs more than 64 KiB of LDS; otherwise as pentago_solve_section
- * (the result does not depend on the shape). */
+/* The tile autotuner: times every tile shape the section admits with HIP
+ * events on hip_stream, remembers the fastest for this section geometry
+ * (later pentago_solve_section calls with the same geometry use it;
+ * pentago_solve_sections uses its lines per tile) and leaves out holding the
+ * sweep's result.  Synchronises the stream.  shape and best_ms may be NULL. */
+int pentago_autotune_section(pentago_section s, const pentago_superinfo *const child[4],
+                             pentago_superinfo *out, void *hip_stream, pentago_tile_shape *shape,
+                             float *best_ms);
+
+/* pentago_solve_section with an explicit tile shape (for tuning and tests).
+ * ERANGE when the shape is outside the ranges above or its tile needs more
+ * than 64 KiB of LDS; otherwise as pentago_solve_section (the result does not
+ * depend on the shape). */
 int pentago_solve_section_shape(pentago_section s, const pentago_superinfo *const child[4],
-                                pentago_superinfo *out, void *hip_stream, int tile_lines,
-                                int tile_threads);
+                                pentago_superinfo *out, void *hip_stream,
+                                const pentago_tile_shape *shape);
 
 /* One section of a batch: its counts, its four child tables as for
  * pentago_solve_section, and its output. */

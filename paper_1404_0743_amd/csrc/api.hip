@@ -176,10 +176,11 @@ void section_shape_of(const pentago_section &s, int m[4])
 }
 
 // Build the sweep job of one section.  `force_d` >= 0 picks the staged
-// dimension; G > 0 the lines per tile and force_threads > 0 the workgroup
-// size (for the tile autotuner).
+// dimension; G > 0 the lines per tile, force_threads > 0 the workgroup
+// size and force_order >= 0 the tile order (for the tile autotuner).
 int make_job(const pentago_section &s, const pentago_superinfo *const child[4],
-             pentago_superinfo *out, SweepJob *J, int force_d, int forceG, int force_threads)
+             pentago_superinfo *out, SweepJob *J, int force_d, int forceG, int force_threads,
+             int force_order)
 {
     if (!section_valid(s)) return fail(PENTAGO_EINVAL, "invalid section counts");
     if (!out) return fail(PENTAGO_EINVAL, "out is NULL");
@@ -229,6 +230,7 @@ int make_job(const pentago_section &s, const pentago_superinfo *const child[4],
     int G = 8;
     const TileShape tuned = tuned_tile_shape(*J);
     J->threads = force_threads > 0 ? force_threads : tuned.lines > 0 ? tuned.threads : 256;
+    J->order = force_order >= 0 ? force_order : tuned.lines > 0 ? tuned.order : 0;
     if (forceG > 0) G = forceG;
     else if (tuned.lines > 0) G = tuned.lines;
     else {

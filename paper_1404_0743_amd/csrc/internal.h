@@ -20,13 +20,15 @@ pentago_section child_of(const pentago_section &s, int j);
 void section_shape_of(const pentago_section &s, int m[4]);
 uint64_t host_block_offset(const int *m, const int *idx);
 int make_job(const pentago_section &s, const pentago_superinfo *const child[4],
-             pentago_superinfo *out, SweepJob *J, int force_d, int forceG, int force_threads = 0);
+             pentago_superinfo *out, SweepJob *J, int force_d, int forceG, int force_threads = 0,
+             int force_order = -1);
 size_t prep_bytes(const SweepJob &J, int j);
 int run_job(SweepJob &J, const DevTables &T, hipStream_t st);
 // Tile shape of a section geometry chosen by the autotuner (0 lines: none).
 struct TileShape {
     int lines;
     int threads;
+    int order;
 };
 TileShape tuned_tile_shape(const SweepJob &J);
 void remember_tile_shape(const SweepJob &J, TileShape t);

@@ -53,6 +53,7 @@ struct SweepJob {
     long long ntiles;
     int lds_bytes;     // dynamic LDS needed by one tile
     int threads;       // workgroup size of the one-section sweep (256 or 512)
+    int order;         // tile order of the one-section sweep (0 natural, 1 by XCD)
 };
 
 // Host launchers (sweep.hip, endgame.hip).

@@ -597,7 +597,14 @@ template <int D, int NT>
 __global__ void __launch_bounds__(NT, NT == 512 ? 6 : 1) sweep_kernel(SweepJob J, DevTables T)
 {
     extern __shared__ uint4 lds[];
-    sweep_tile<D>(J, T, blockIdx.x, (void *)lds);
+    uint32_t tile = blockIdx.x;
+    if (J.order == 1) {
+        // workgroups go to the 8 XCDs in turn: XCD x = b % 8 takes the x-th
+        // contiguous range of tiles (ranges differ in size by at most one)
+        const uint32_t n = (uint32_t)J.ntiles, per = n >> 3, rem = n & 7u, x = tile & 7u;
+        tile = x * per + min(x, rem) + (tile >> 3);
+    }
+    sweep_tile<D>(J, T, tile, (void *)lds);
 }
 
 // Many sections in one persistent launch: workgroups take tiles from a

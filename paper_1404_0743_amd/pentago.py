@@ -22,6 +22,10 @@ class PentagoError(RuntimeError):
         self.code = code
 
 
+class TileShape(ctypes.Structure):
+    _fields_ = [("lines", ctypes.c_int32), ("threads", ctypes.c_int32), ("order", ctypes.c_int32)]
+
+
 class Section(ctypes.Structure):
     _fields_ = [("black", ctypes.c_uint8 * 4), ("white", ctypes.c_uint8 * 4)]
 
@@ -63,8 +67,8 @@ _SIGS = {
     "pentago_child_section": ([Section, ctypes.c_int, _P], ctypes.c_int),
     "pentago_solve_section": ([Section, _P, _P, _P], ctypes.c_int),
     "pentago_solve_sections": ([_P, ctypes.c_size_t, _P], ctypes.c_int),
-    "pentago_autotune_section": ([Section, _P, _P, _P, _P, _P, _P], ctypes.c_int),
-    "pentago_solve_section_shape": ([Section, _P, _P, _P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "pentago_autotune_section": ([Section, _P, _P, _P, _P, _P], ctypes.c_int),
+    "pentago_solve_section_shape": ([Section, _P, _P, _P, _P], ctypes.c_int),
     "pentago_plan_create": ([_P, ctypes.c_size_t, _P], ctypes.c_int),
     "pentago_plan_launch": ([_P, _P], ctypes.c_int),
     "pentago_plan_launch_graph": ([_P, _P], ctypes.c_int),
@@ -208,23 +212,23 @@ def pentago_solve_section(counts, children, out, stream=None):
 
 def pentago_autotune_section(counts, children, out, stream=None):
     """Time the tile shapes of this section geometry, remember the fastest;
-    returns (tile lines, workgroup size, best ms).  out holds the sweep's
+    returns ({"lines", "threads", "order"}, best ms).  out holds the sweep's
     result afterwards."""
     ch = (ctypes.c_void_p * 4)(*[None if c is None else c.data_ptr() for c in children])
-    g = ctypes.c_int()
-    nt = ctypes.c_int()
+    shape = TileShape()
     ms = ctypes.c_float()
     _check(lib().pentago_autotune_section(section(counts), ch, _dev_ptr(out), _stream(stream),
-                                          ctypes.byref(g), ctypes.byref(nt), ctypes.byref(ms)),
+                                          ctypes.byref(shape), ctypes.byref(ms)),
            "pentago_autotune_section")
-    return g.value, nt.value, ms.value
+    return {"lines": shape.lines, "threads": shape.threads, "order": shape.order}, ms.value
 
 
-def pentago_solve_section_shape(counts, children, out, tile_lines, tile_threads, stream=None):
-    """The sweep with an explicit tile shape (lines per tile, threads)."""
+def pentago_solve_section_shape(counts, children, out, lines, threads, order=0, stream=None):
+    """The sweep with an explicit tile shape."""
     ch = (ctypes.c_void_p * 4)(*[None if c is None else c.data_ptr() for c in children])
+    shape = TileShape(int(lines), int(threads), int(order))
     _check(lib().pentago_solve_section_shape(section(counts), ch, _dev_ptr(out), _stream(stream),
-                                             int(tile_lines), int(tile_threads)),
+                                             ctypes.byref(shape)),
            "pentago_solve_section_shape")
 
 

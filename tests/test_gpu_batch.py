@@ -108,8 +108,9 @@ def test_autotuned_tiles_give_same_bytes(P):
     ch = solve(P, O.child_counts(counts, 3), [None] * 4)
     ref = solve(P, counts, [None, None, None, ch])
     out = torch.full_like(ref, -1)
-    g, nt, ms = P.pentago_autotune_section(counts, [None, None, None, ch], out)
-    assert 1 <= g <= 8 and nt in (256, 512) and ms > 0
+    shape, ms = P.pentago_autotune_section(counts, [None, None, None, ch], out)
+    assert 1 <= shape["lines"] <= 8 and shape["threads"] in (256, 512) and shape["order"] in (0, 1)
+    assert ms > 0
     assert torch.equal(ref, out)
     out2 = solve(P, counts, [None, None, None, ch])
     torch.cuda.synchronize()
@@ -134,19 +135,19 @@ def test_every_tile_shape_gives_same_bytes(P, counts):
     torch.cuda.synchronize()
     tried = 0
     out = torch.empty_like(ref)
-    for threads in (256, 512):
-        for lines in range(1, 9):
-            out.fill_(-1)
-            try:
-                P.pentago_solve_section_shape(counts, ch, out, lines, threads)
-            except P.PentagoError as e:
-                assert e.code == P.ERANGE  # tile over 64 KiB of LDS
-                continue
-            torch.cuda.synchronize()
-            assert torch.equal(ref, out), (lines, threads)
-            tried += 1
-    assert tried >= 4
-    with pytest.raises(P.PentagoError):
-        P.pentago_solve_section_shape(counts, ch, out, 9, 256)
-    with pytest.raises(P.PentagoError):
-        P.pentago_solve_section_shape(counts, ch, out, 4, 128)
+    for order in (0, 1):
+        for threads in (256, 512):
+            for lines in range(1, 9):
+                out.fill_(-1)
+                try:
+                    P.pentago_solve_section_shape(counts, ch, out, lines, threads, order)
+                except P.PentagoError as e:
+                    assert e.code == P.ERANGE  # tile over 64 KiB of LDS
+                    continue
+                torch.cuda.synchronize()
+                assert torch.equal(ref, out), (lines, threads, order)
+                tried += 1
+    assert tried >= 8
+    for bad in ((9, 256, 0), (4, 128, 0), (4, 256, 2)):
+        with pytest.raises(P.PentagoError):
+            P.pentago_solve_section_shape(counts, ch, out, *bad)
