@@ -14,6 +14,9 @@ Oracle functions and what they follow (Irving, arXiv:1404.0743):
                               orderings, 8^4 blocks) and O4: the Section II
                               recurrence per entry on concrete boards, children read
                               from the (n+1)-stone child sections.
+  sym_*, section_transform -- the board symmetries (D4 of Section III) acting on
+                              sections and on their tables, bit by bit on concrete
+                              boards (Section IV computes only D4-minimal sections).
 Parity status: pinned (see tests/test_oracle_*.py); nothing here is unpinned.
 """
 import ctypes
@@ -68,6 +71,10 @@ def lib():
         L.po_section_solve.argtypes = [P, P, P, ctypes.c_long, P, ctypes.c_int]
         L.po_section_all_indices.argtypes = [P, P]
         L.po_section_all_indices.restype = ctypes.c_long
+        L.po_sym_cells.argtypes = [ctypes.c_int, P]
+        L.po_sym_quadrants.argtypes = [ctypes.c_int, P]
+        L.po_sym_counts.argtypes = [P, ctypes.c_int, P]
+        L.po_section_transform.argtypes = [P, P, ctypes.c_int, P, ctypes.c_long, P, ctypes.c_int]
         L.po_init()
         _lib = L
     return _lib
@@ -232,6 +239,51 @@ def section_solve(counts, children, idx=None, nthreads=None):
                                 nthreads or default_threads())
     if rc:
         raise ValueError("section solve failed (%d)" % rc)
+    return out
+
+
+# ------------------------------------------------------------- board symmetries
+
+def sym_cells(sym):
+    """Cell map of board symmetry sym = r + 4*f (mirror left-right if f, then
+    r counter-clockwise quarter turns): the stone on cell c moves to out[c]."""
+    out = np.zeros(36, np.int32)
+    if lib().po_sym_cells(int(sym), _ptr(out)):
+        raise ValueError("bad symmetry")
+    return out
+
+
+def sym_quadrants(sym):
+    out = np.zeros(4, np.int32)
+    if lib().po_sym_quadrants(int(sym), _ptr(out)):
+        raise ValueError("bad symmetry")
+    return tuple(int(x) for x in out)
+
+
+def sym_counts(counts, sym):
+    """Counts of the image section under board symmetry sym."""
+    out = np.zeros(8, np.int32)
+    if lib().po_sym_counts(_ptr(_counts(counts)), int(sym), _ptr(out)):
+        raise ValueError("invalid section or symmetry")
+    return tuple((int(out[j]), int(out[4 + j])) for j in range(4))
+
+
+def section_transform(counts, table, sym, idx=None, nthreads=None):
+    """Table of the image section sym(counts) from the whole table of
+    `counts` (blocked order), entry by entry and bit by bit.  idx: (n, 4)
+    indices of the image section, or None for all of it (blocked order)."""
+    dst = sym_counts(counts, sym)
+    if idx is None:
+        idx = section_all_indices(dst)
+    idx = np.ascontiguousarray(idx, dtype=np.int32).reshape(-1, 4)
+    src = np.ascontiguousarray(table, dtype=np.uint64)
+    if src.shape != (section_entries(counts), 8):
+        raise ValueError("source table has the wrong shape")
+    out = np.zeros((len(idx), 8), np.uint64)
+    rc = lib().po_section_transform(_ptr(_counts(counts)), _ptr(src), int(sym), _ptr(idx), len(idx),
+                                    _ptr(out), nthreads or default_threads())
+    if rc:
+        raise ValueError("section transform failed (%d)" % rc)
     return out
 
 

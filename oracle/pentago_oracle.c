@@ -610,6 +610,116 @@ long po_section_all_indices(const int *counts, int *idx)
     return n;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Board symmetries and section tables (Section III: the group G = L x| D4;  */
+/* Section IV: only D4-minimal sections are computed)                         */
+/* ------------------------------------------------------------------------ */
+
+/* The 8 board symmetries, numbered sym = r + 4*f: mirror left-right when f
+   is set ((row, col) -> (row, 5 - col)), then r quarter turns of the whole
+   board counter-clockwise ((row, col) -> (5 - col, row)).  Writes the cell
+   map: the stone on cell c moves to cell perm[c]. */
+int po_sym_cells(int sym, int *perm)
+{
+    if (sym < 0 || sym > 7) return -1;
+    for (int c = 0; c < 36; c++) {
+        int r = c / 6, col = c % 6;
+        if (sym & 4) col = 5 - col;
+        for (int t = 0; t < (sym & 3); t++) {
+            int nr = 5 - col, nc = r;
+            r = nr;
+            col = nc;
+        }
+        perm[c] = 6 * r + col;
+    }
+    return 0;
+}
+
+/* Quadrant position map of a symmetry: quadrant q moves to qmap[q] (read off
+   where the centre cell of q goes). */
+int po_sym_quadrants(int sym, int *qmap)
+{
+    int perm[36];
+    if (po_sym_cells(sym, perm)) return -1;
+    for (int q = 0; q < 4; q++) qmap[q] = quadrant_of_cell(perm[cell_of(q, 4)]);
+    return 0;
+}
+
+/* Counts of the image section sym(s): the counts of quadrant q move to
+   quadrant qmap[q]. */
+int po_sym_counts(const int *counts, int sym, int *out)
+{
+    int qmap[4];
+    if (!section_valid(counts) || po_sym_quadrants(sym, qmap)) return -1;
+    for (int q = 0; q < 4; q++) {
+        out[qmap[q]] = counts[q];
+        out[4 + qmap[q]] = counts[4 + q];
+    }
+    return 0;
+}
+
+typedef struct {
+    int src_counts[8], dst_counts[8];
+    int perm[36];
+    const uint64_t *src;
+    const int *idx;
+    uint64_t *out;
+} sym_ctx;
+
+/* One entry of the image table, bit by bit.  The values of a position and of
+   its image under a board symmetry are equal (the rules do not distinguish
+   them), so bit G of the image entry is the value of the board G.b', where b'
+   is the image entry's board, and that board's preimage under the symmetry
+   is a concrete board of the source section: canonicalise its quadrants and
+   read the source table as child_value does. */
+static void sym_item(void *vctx, long i)
+{
+    sym_ctx *c = (sym_ctx *)vctx;
+    uint8_t dst[36];
+    po_section_board(c->dst_counts, c->idx + 4 * i, dst);
+    uint64_t *out = c->out + 8 * i;
+    memset(out, 0, 8 * sizeof(uint64_t));
+    for (int G = 0; G < 256; G++) {
+        uint8_t gd[36], pre[36];
+        po_apply(dst, G, gd);
+        for (int cell = 0; cell < 36; cell++) pre[cell] = gd[c->perm[cell]];
+        int idx[4], g = 0;
+        for (int j = 0; j < 4; j++) {
+            int code = 0;
+            for (int l = 8; l >= 0; l--) code = 3 * code + pre[cell_of(j, l)];
+            int k;
+            int mn = po_canon(code, &k);
+            idx[j] = CODE_INDEX[mn];
+            g |= ((4 - k) & 3) << (2 * j);
+        }
+        const uint64_t *t = c->src + 8 * po_section_offset(c->src_counts, idx);
+        int w = (int)((t[g >> 6] >> (g & 63)) & 1);
+        int nl = (int)((t[4 + (g >> 6)] >> (g & 63)) & 1);
+        set_bits(out, G, w ? 1 : (nl ? 0 : -1));
+    }
+}
+
+/* Entries idx (n x 4, indices of the image section sym(s)) of the table of
+   sym(s), from the whole table src of section s (blocked order).  Returns 0,
+   or -1 for an invalid section or symmetry, -3 for an index out of range. */
+int po_section_transform(const int *counts, const uint64_t *src, int sym, const int *idx, long n,
+                         uint64_t *out, int nthreads)
+{
+    sym_ctx c;
+    memcpy(c.src_counts, counts, sizeof(c.src_counts));
+    if (po_sym_counts(counts, sym, c.dst_counts) || po_sym_cells(sym, c.perm)) return -1;
+    long m[4];
+    section_shape(c.dst_counts, m);
+    for (long i = 0; i < n; i++)
+        for (int j = 0; j < 4; j++)
+            if (idx[4 * i + j] < 0 || idx[4 * i + j] >= m[j]) return -3;
+    c.src = src;
+    c.idx = idx;
+    c.out = out;
+    run_pool(sym_item, &c, n, nthreads);
+    return 0;
+}
+
 int po_init(void)
 {
     if (NLINES) return 0;
