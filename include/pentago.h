@@ -98,6 +98,44 @@ int pentago_section_board(pentago_section s, const uint32_t idx[4], pentago_boar
  * quadrant j is full. */
 int pentago_child_section(pentago_section s, int j, pentago_section *child);
 
+/* ------------------------------------------------------- board symmetries */
+
+/* The 8 board symmetries (Section III: with the quadrant turns L they form
+ * the group G of approximate symmetries; values are unchanged by them).
+ * sym = r + 4 f, 0 <= sym <= 7: mirror the board left-right when f is set
+ * ((row, col) -> (row, 5 - col)), then turn the whole board r quarter turns
+ * counter-clockwise ((row, col) -> (5 - col, row)).  Quadrant q moves to
+ * quadrant pi(q): the rotation r = 1 sends 0 -> 2, 1 -> 0, 2 -> 3, 3 -> 1,
+ * the mirror 0 <-> 1, 2 <-> 3.
+ *
+ * *image = the section holding the images of the boards of s: the counts of
+ * quadrant q move to quadrant pi(q).  EINVAL for invalid counts or sym. */
+int pentago_section_image(pentago_section s, int sym, pentago_section *image);
+
+/* The representative of s under the board symmetries (Section IV: only
+ * sections whose count tuple ((b0,w0),(b1,w1),(b2,w2),(b3,w3)) is least in
+ * lexicographic order among its images are computed): *rep is that least
+ * image and *sym a symmetry with pentago_section_image(*rep, *sym) == s
+ * (sym = 0 when s is its own representative).  Host only. */
+int pentago_section_standardize(pentago_section s, pentago_section *rep, int *sym);
+
+/* The table of pentago_section_image(s, sym) from the table of s (Section
+ * III: when the representative of a board changes, its table is shifted,
+ * its dimensions transposed and, for a reflection, reversed).
+ *   table  device, entries(s) x 64 B, blocked layout (read)
+ *   out    device, entries(image) x 64 B (the same count), written completely;
+ *          must not overlap table
+ * Bit G of image entry e' is bit g of the source entry e whose boards map
+ * onto e' (quadrant i of e goes to quadrant pi(i) of e', its pattern mirrored
+ * for a reflection and turned to its rotation-minimal form), where
+ * g_i = sign (G_pi(i) - h_pi(i)), sign = -1 for a reflection, and h_j turns
+ * the local image of the source pattern to the pattern of e' (h_j = 1 for
+ * every non-symmetric pattern under a rotation).  Stream-ordered and
+ * asynchronous.  EINVAL for invalid counts, sym, NULL or overlapping
+ * pointers; ERANGE for sections of 2^32 entries or more. */
+int pentago_section_transform(pentago_section s, const pentago_superinfo *table, int sym,
+                              pentago_superinfo *out, void *hip_stream);
+
 /* ---------------------------------------------------------------- sweep */
 
 /* The n+1 -> n sweep of one section (Section II recurrence on Section III
@@ -112,6 +150,23 @@ int pentago_child_section(pentago_section s, int j, pentago_section *child);
  * section or NULL out; ENOCHILD for a missing child that is needed. */
 int pentago_solve_section(pentago_section s, const pentago_superinfo *const child[4],
                           pentago_superinfo *out, void *hip_stream);
+
+/* The sweep of section s with its children held only as their
+ * representatives under the board symmetries (Section IV: only sections
+ * whose counts are least among their images are computed).
+ *   rep[j]  device table of the representative of pentago_child_section(s, j)
+ *           (pentago_section_standardize), or NULL when quadrant j is full or
+ *           its child is a 36-stone section evaluated on demand.
+ *   out     as in pentago_solve_section.
+ * A child that is its own representative is read in place; any other child
+ * is first rebuilt from its representative by pentago_section_transform into
+ * scratch memory allocated stream-ordered on hip_stream (hipMallocAsync) and
+ * released after the sweep, so the call needs that much device memory free.
+ * The result is bit for bit the pentago_solve_section result with the
+ * children themselves.  Errors as pentago_solve_section, plus EDEVICE when
+ * the scratch allocation fails. */
+int pentago_solve_section_d4(pentago_section s, const pentago_superinfo *const rep[4],
+                             pentago_superinfo *out, void *hip_stream);
 
 /* Tile shape of the sweep: lines of the section along the staged quadrant
  * per tile (1..8), threads per workgroup (256 or 512), and the order in

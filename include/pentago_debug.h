@@ -33,6 +33,18 @@ int pentago_debug_shift(const pentago_set256 *in, int d, int k, pentago_set256 *
  * stones (self-inverse; identity for d = 3). */
 int pentago_debug_swap3(const pentago_set256 *in, int d, pentago_set256 *out);
 
+/* The image of a table under board symmetry sym (numbered as in
+ * pentago_section_image): out(G) = in(g) with g_i = sign * (G_{pi(i)} - h[pi(i)]),
+ * where pi moves quadrant i to quadrant pi(i), sign is -1 for the reflections
+ * (sym >= 4) and h[j] are the turns of image quadrant j (Section III). */
+int pentago_debug_sym(const pentago_set256 *in, int sym, const int h[4], pentago_set256 *out);
+
+/* The pattern map of board symmetry sym for the (black, white) class: image
+ * pattern `index` comes from source pattern *src_index, whose local image
+ * (mirror if sym >= 4, then sym & 3 counter-clockwise turns) is the image
+ * pattern turned *h more times (Section III). */
+int pentago_debug_sym_pattern(int sym, int black, int white, int index, int *src_index, int *h);
+
 /* Rotation-minimal pattern of a quadrant code: its index in its (black,
  * white) class and the least number of counter-clockwise turns k taking the
  * code to it (Section IV). */

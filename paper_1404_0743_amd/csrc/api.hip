@@ -74,7 +74,7 @@ int device_tables(DevTables *out)
         size_t bytes;
         void **dst;
     };
-    void *canon, *qinfo, *lm, *dn, *dr, *sel, *cref, *uref, *smask, *srank;
+    void *canon, *qinfo, *lm, *dn, *dr, *sel, *cref, *uref, *smask, *srank, *symmap;
     Up ups[] = {{H.canon.data(), H.canon.size() * 2, &canon},
                 {H.qinfo.data(), H.qinfo.size() * sizeof(QInfo), &qinfo},
                 {H.lm.data(), H.lm.size() * sizeof(LineMasks), &lm},
@@ -84,7 +84,8 @@ int device_tables(DevTables *out)
                 {H.chunk_ref.data(), H.chunk_ref.size() * 2, &cref},
                 {H.u_ref.data(), H.u_ref.size() * 4, &uref},
                 {submask.data(), submask.size() * 2, &smask},
-                {subrank.data(), subrank.size() * 2, &srank}};
+                {subrank.data(), subrank.size() * 2, &srank},
+                {H.symmap.data(), H.symmap.size() * 2, &symmap}};
     for (Up &u : ups) {
         e = hipMalloc(&p, u.bytes);
         if (e != hipSuccess) return hip_fail(e, "hipMalloc(tables)");
@@ -102,6 +103,7 @@ int device_tables(DevTables *out)
     T.u_ref = (const uint32_t *)uref;
     T.dag_sub_mask = (const uint16_t *)smask;
     T.dag_sub_rank = (const uint16_t *)srank;
+    T.symmap = (const uint16_t *)symmap;
     g_dev_tables[dev] = T;
     *out = T;
     return 0;

@@ -59,6 +59,27 @@ int pentago_debug_swap3(const pentago_set256 *in, int d, pentago_set256 *out)
     return 0;
 }
 
+int pentago_debug_sym(const pentago_set256 *in, int sym, const int h[4], pentago_set256 *out)
+{
+    if (!in || !out || !h || sym < 0 || sym > 7) return fail(PENTAGO_EINVAL, "invalid arguments");
+    Set256 x = from_abi(in);
+    sym_apply_rt(x, sym, h);
+    to_abi(x, out);
+    return 0;
+}
+
+int pentago_debug_sym_pattern(int sym, int black, int white, int index, int *src_index, int *h)
+{
+    const HostTables &H = host_tables();
+    if (sym < 0 || sym > 7 || black < 0 || white < 0 || black + white > 9 || !src_index || !h)
+        return fail(PENTAGO_EINVAL, "invalid arguments");
+    if (index < 0 || index >= H.class_size[black][white]) return fail(PENTAGO_EINVAL, "index out of range");
+    const uint16_t e = H.symmap[sym * kPatterns + H.class_start[black][white] + index];
+    *src_index = e & 0xfff;
+    *h = e >> 12;
+    return 0;
+}
+
 int pentago_debug_canon(int code, int *index, int *k)
 {
     if (code < 0 || code >= 19683 || !index || !k) return fail(PENTAGO_EINVAL, "invalid arguments");

@@ -110,6 +110,50 @@ __device__ __forceinline__ Set256 set_from(const uint4 *p)
     return x;
 }
 
+// ---------------------------------------------------------------------------
+// Whole-entry memory access by quads.  Each lane works on one entry (64 B,
+// four 16-byte pieces).  The four lanes of a quad transpose their pieces in
+// registers (two exchange stages of DPP quad permutations), so that in each
+// of four load or store instructions the quad moves one whole entry; when
+// quad q's lanes hold entries q, q + 16, q + 32, q + 48 of 64 neighbours,
+// each instruction of a wave moves 16 neighbouring entries, 1 KB in order.
+// ---------------------------------------------------------------------------
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t quad_perm(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, true);
+}
+
+// quad lanes [1,0,3,2] (X = 1) or [2,3,0,1] (X = 2)
+template <int X>
+__device__ __forceinline__ uint4 quad_xor(uint4 a)
+{
+    constexpr int ctrl = X == 1 ? 0xB1 : 0x4E;
+    return make_uint4(quad_perm<ctrl>(a.x), quad_perm<ctrl>(a.y), quad_perm<ctrl>(a.z), quad_perm<ctrl>(a.w));
+}
+
+// One exchange stage: slot p of lane l takes slot p ^ X of lane l ^ X when
+// bit X of l differs from bit X of p.
+template <int X>
+__device__ __forceinline__ void quad_stage(uint4 (&r)[4], int l)
+{
+    uint4 t[4];
+#pragma unroll
+    for (int p = 0; p < 4; p++) t[p] = quad_xor<X>(r[p ^ X]);
+#pragma unroll
+    for (int p = 0; p < 4; p++)
+        if ((l ^ p) & X) r[p] = t[p];
+}
+
+// After this, slot p of quad lane l holds piece l of quad lane p's entry.
+__device__ __forceinline__ void quad_transpose(uint4 (&r)[4], int l)
+{
+    quad_stage<2>(r, l);
+    quad_stage<1>(r, l);
+}
+
+
 // Clear n work-queue counters (a kernel, not a memset, so the sequence can
 // be captured in a graph).
 static __global__ void zero_counter_kernel(unsigned long long *c, int n)

@@ -28,6 +28,20 @@ struct DevTables {
     int dag_sub_off[11];        // start of layout e in both (2^e entries each)
     int dag_sub_start[11][12];  // start of size s within layout e
     int dag_sub_max[11];        // largest C(e, s)
+    const uint16_t *symmap;     // [8 * kPatterns]: source pattern | turns << 12 per symmetry
+};
+
+// The table of the image section sym(s) from the table of s (Section III,
+// transforms of tables under the board symmetries).
+struct SymJob {
+    int sym;
+    int m[4];           // image shape
+    int sm[4];          // source shape
+    int qb[4];          // first QInfo index of each image quadrant class
+    int nb[4];          // blocks of the image per dimension
+    long long nchunks;  // image blocks x 4 quarters
+    const uint4 *src;
+    uint4 *dst;
 };
 
 // One section sweep (Section IV): a parent section, its child sections and
@@ -56,8 +70,9 @@ struct SweepJob {
     int order;         // tile order of the one-section sweep (0 natural, 1 by XCD)
 };
 
-// Host launchers (sweep.hip, endgame.hip).
+// Host launchers (sweep.hip, endgame.hip, symmetry.hip).
 hipError_t launch_sweep(const SweepJob &job, const DevTables &T, hipStream_t s);
+hipError_t launch_transform(const SymJob &job, const DevTables &T, hipStream_t s);
 // Prepare the A/B child terms of dimension j (j in emask, j != d).
 hipError_t launch_prep(const SweepJob &job, int j, const DevTables &T, hipStream_t s);
 hipError_t launch_prep_batch(const SweepJob *dev_jobs, const int *dev_unit,

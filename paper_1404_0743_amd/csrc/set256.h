@@ -192,6 +192,145 @@ PG_HD void swap_with3_rt(Set256 &x, int D)
 }
 
 // ------------------------------------------------------------------------
+// Board symmetries acting on tables (Section III: a change of the
+// representative under G = L x| D4 transforms f_b into f_{gb} by cyclic
+// shifts, transpositions of dimensions and reflections).
+//
+// sym = r + 4 f: mirror the board left-right when f is set, then turn the
+// whole board r quarter turns counter-clockwise.  Quadrant q moves to
+// sym_quadrant(sym, q); every quadrant's cells move by the same local map
+// (mirror, then r turns), and a reflection reverses the sense of quadrant
+// turns.  For a board b and its image b', the value of g.b equals the value
+// of g'.b' where g'_{pi(i)} = sign * g_i (pi = sym_quadrant, sign -1 for a
+// reflection); when b' is rotation-minimal only up to turns h of its
+// quadrants, g' gains + h.  So the image table is
+//   out(G) = in(g),  g_i = sign * (G_{pi(i)} - h_{pi(i)}),
+// computed as: move dimension i to position pi(i), negate every dimension
+// for a reflection, shift dimension j by h_j.
+// ------------------------------------------------------------------------
+
+PG_HD constexpr int sym_quadrant(int sym, int q)
+{
+    int qr = q >> 1, qc = q & 1;
+    if (sym & 4) qc = 1 - qc;
+    for (int t = 0; t < (sym & 3); t++) {
+        const int nr = 1 - qc, nc = qr;  // a counter-clockwise quarter turn
+        qr = nr;
+        qc = nc;
+    }
+    return 2 * qr + qc;
+}
+
+// the quadrant that sym moves onto quadrant j
+PG_HD constexpr int sym_source(int sym, int j)
+{
+    int q = 0;
+    for (int i = 0; i < 4; i++)
+        if (sym_quadrant(sym, i) == j) q = i;
+    return q;
+}
+
+// Reflections are involutions; a rotation by r is undone by 4 - r.
+PG_HD constexpr int sym_inverse(int sym) { return (sym & 4) ? sym : (4 - sym) & 3; }
+
+// Exchanges with dimension 3 (swap_with3) that move dimension i to position
+// sym_quadrant(sym, i): positions 0, 1, 2 are filled in turn, each with at
+// most two exchanges.
+struct SymSteps {
+    int n;
+    int a[6];
+};
+
+PG_HD constexpr SymSteps sym_steps(int sym)
+{
+    SymSteps st{0, {0, 0, 0, 0, 0, 0}};
+    int at[4] = {0, 1, 2, 3};  // source dimension now at each position
+    for (int t = 0; t < 3; t++) {
+        const int want = sym_source(sym, t);
+        if (at[t] == want) continue;
+        if (at[3] != want) {
+            int u = 0;
+            for (int p = 0; p < 3; p++)
+                if (at[p] == want) u = p;
+            const int x = at[u];
+            at[u] = at[3];
+            at[3] = x;
+            st.a[st.n++] = u;
+        }
+        const int x = at[t];
+        at[t] = at[3];
+        at[3] = x;
+        st.a[st.n++] = t;
+    }
+    return st;
+}
+
+// out(g) = in(g with g_D replaced by -g_D): values 1 and 3 trade places.
+template <int D>
+PG_HD void negate_dim(Set256 &x)
+{
+    if constexpr (D == 0) {
+#pragma unroll
+        for (int w = 0; w < 8; w++) x.w[w] = bfi(0x55555555u, x.w[w], bfi(0x22222222u, x.w[w] >> 2, x.w[w] << 2));
+    } else if constexpr (D == 1) {
+#pragma unroll
+        for (int w = 0; w < 8; w++) x.w[w] = bfi(0x0f0f0f0fu, x.w[w], bfi(0x00f000f0u, x.w[w] >> 8, x.w[w] << 8));
+    } else if constexpr (D == 2) {
+        // g2 = 1 (upper half of the even word) <-> g2 = 3 (upper half of the odd word)
+#pragma unroll
+        for (int g3 = 0; g3 < 4; g3++) {
+            const uint32_t a = x.w[2 * g3], b = x.w[2 * g3 + 1];
+            x.w[2 * g3] = bfi(0xffff0000u, b, a);
+            x.w[2 * g3 + 1] = bfi(0xffff0000u, a, b);
+        }
+    } else {
+        // word pair 1 <-> word pair 3
+        uint32_t t = x.w[2]; x.w[2] = x.w[6]; x.w[6] = t;
+        t = x.w[3]; x.w[3] = x.w[7]; x.w[7] = t;
+    }
+}
+
+// The image table under board symmetry SYM (see above); h[j] are the turns
+// of image quadrant j.
+template <int SYM>
+PG_HD void sym_apply(Set256 &x, const int h[4])
+{
+    constexpr SymSteps st = sym_steps(SYM);
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+        if (i < st.n) {
+            if (st.a[i] == 0) swap_with3<0>(x);
+            else if (st.a[i] == 1) swap_with3<1>(x);
+            else swap_with3<2>(x);
+        }
+    }
+    if constexpr ((SYM & 4) != 0) {
+        negate_dim<0>(x);
+        negate_dim<1>(x);
+        negate_dim<2>(x);
+        negate_dim<3>(x);
+    }
+    x = shift_dim(x, 0, h[0]);
+    x = shift_dim(x, 1, h[1]);
+    x = shift_dim(x, 2, h[2]);
+    x = shift_dim(x, 3, h[3]);
+}
+
+PG_HD void sym_apply_rt(Set256 &x, int sym, const int h[4])
+{
+    switch (sym & 7) {
+    case 0: sym_apply<0>(x, h); break;
+    case 1: sym_apply<1>(x, h); break;
+    case 2: sym_apply<2>(x, h); break;
+    case 3: sym_apply<3>(x, h); break;
+    case 4: sym_apply<4>(x, h); break;
+    case 5: sym_apply<5>(x, h); break;
+    case 6: sym_apply<6>(x, h); break;
+    default: sym_apply<7>(x, h); break;
+    }
+}
+
+// ------------------------------------------------------------------------
 // Five in a row over L (Section III: the set of g for which g.b has five in
 // a row of one colour).
 //

@@ -201,48 +201,6 @@ __device__ __forceinline__ void or_rotated(Set256 &acc, const uint32_t *p, int k
     }
 }
 
-// ---------------------------------------------------------------------------
-// Stores of the parent pass.  Each lane computes one parent entry (64 B, four
-// 16-byte pieces).  The four lanes of a quad then transpose their pieces in
-// registers (two exchange stages of DPP quad permutations), so that in each
-// of four store instructions the quad writes one whole entry and the 16 quads
-// of a wave write 16 neighbouring entries: full, contiguous 1 KB stores.
-// ---------------------------------------------------------------------------
-
-template <int CTRL>
-__device__ __forceinline__ uint32_t quad_perm(uint32_t x)
-{
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, true);
-}
-
-// quad lanes [1,0,3,2] (X = 1) or [2,3,0,1] (X = 2)
-template <int X>
-__device__ __forceinline__ uint4 quad_xor(uint4 a)
-{
-    constexpr int ctrl = X == 1 ? 0xB1 : 0x4E;
-    return make_uint4(quad_perm<ctrl>(a.x), quad_perm<ctrl>(a.y), quad_perm<ctrl>(a.z), quad_perm<ctrl>(a.w));
-}
-
-// One exchange stage: slot p of lane l takes slot p ^ X of lane l ^ X when
-// bit X of l differs from bit X of p.
-template <int X>
-__device__ __forceinline__ void quad_stage(uint4 (&r)[4], int l)
-{
-    uint4 t[4];
-#pragma unroll
-    for (int p = 0; p < 4; p++) t[p] = quad_xor<X>(r[p ^ X]);
-#pragma unroll
-    for (int p = 0; p < 4; p++)
-        if ((l ^ p) & X) r[p] = t[p];
-}
-
-// After this, slot p of quad lane l holds piece l of quad lane p's entry.
-__device__ __forceinline__ void quad_transpose(uint4 (&r)[4], int l)
-{
-    quad_stage<2>(r, l);
-    quad_stage<1>(r, l);
-}
-
 // Children of one parent along a dimension JD that is not staged: their
 // A/B terms were prepared per child entry by prep_kernel, in the parent's
 // internal layout (64 B each, in the child section's blocked order).

@@ -1,0 +1,254 @@
+// symmetry.hip -- board symmetries acting on sections and on their tables
+// (Section III: the group G = L x| D4 of approximate symmetries, and the
+// transform of a table when the representative of a board changes;
+// Section IV: only sections whose counts are least under the board
+// symmetries are computed, the others are images of those).
+#include "device_common.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace pg {
+
+// One workgroup takes a quarter of one 8^4 block of the image section (up to
+// 1024 entries; each wave 64 neighbouring entries per step).  The entries of
+// an image block are contiguous in the image table.  Lane i works on entry
+// 16 (i & 3) + (i >> 2) of its wave's 64: it finds its source entry (one
+// source block for a rotation, a few for a reflection, which reorders the
+// patterns inside each dimension), the quad loads its four source entries
+// whole, transposes, transforms, transposes back and stores 1 KB runs.
+template <int SYM>
+__global__ void __launch_bounds__(256) transform_kernel(SymJob J, DevTables T)
+{
+    long long blk = (long long)blockIdx.x >> 2;
+    const int quarter = (int)(blockIdx.x & 3u);
+    int corner[4], s[4];
+    {
+        int B[4];
+        B[3] = (int)(blk % J.nb[3]); blk /= J.nb[3];
+        B[2] = (int)(blk % J.nb[2]); blk /= J.nb[2];
+        B[1] = (int)(blk % J.nb[1]); blk /= J.nb[1];
+        B[0] = (int)blk;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            corner[j] = 8 * B[j];
+            s[j] = min(8, J.m[j] - corner[j]);
+        }
+    }
+    const uint32_t base = block_offset(J.m, corner);
+    const int vol = s[0] * s[1] * s[2] * s[3];
+    const int end = min(vol, 1024 * (quarter + 1));
+    // r / s for r < 4096 and s <= 8 as a multiply-high by ceil(2^16 / s):
+    // the error stays below 1/16, under the 1/s gap to the next integer
+    const uint32_t mg1 = (65535u + s[1]) / s[1], mg2 = (65535u + s[2]) / s[2],
+                   mg3 = (65535u + s[3]) / s[3];
+    const uint16_t *map = T.symmap + SYM * kPatterns;
+    const int ql = (int)(threadIdx.x & 3u), qq = (int)((threadIdx.x & 63u) >> 2);
+    for (int r0 = 1024 * quarter + 64 * (int)(threadIdx.x >> 6); r0 < end; r0 += 256) {
+        // a spare lane past the end repeats the last entry (never stored)
+        const int r = min(r0 + 16 * ql + qq, end - 1);
+        const uint32_t q3 = ((uint32_t)r * mg3) >> 16;
+        const uint32_t q2 = (q3 * mg2) >> 16;
+        const uint32_t q1 = (q2 * mg1) >> 16;
+        const int loc[4] = {(int)q1, (int)(q2 - q1 * s[1]), (int)(q3 - q2 * s[2]), (int)(r - q3 * s[3])};
+        int sidx[4], h[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t e = map[J.qb[j] + corner[j] + loc[j]];
+            h[j] = (int)(e >> 12);
+            sidx[sym_source(SYM, j)] = (int)(e & 0xfffu);
+        }
+        const uint32_t off = block_offset(J.sm, sidx);
+        const uint32_t offs[4] = {quad_perm<0x00>(off), quad_perm<0x55>(off), quad_perm<0xAA>(off),
+                                  quad_perm<0xFF>(off)};
+        uint4 v[4];
+#pragma unroll
+        for (int p = 0; p < 4; p++) v[p] = J.src[4 * (size_t)offs[p] + ql];  // piece ql of lane p's entry
+        quad_transpose(v, ql);                                               // own entry, pieces 0..3
+        Set256 W, N;
+        W.w[0] = v[0].x; W.w[1] = v[0].y; W.w[2] = v[0].z; W.w[3] = v[0].w;
+        W.w[4] = v[1].x; W.w[5] = v[1].y; W.w[6] = v[1].z; W.w[7] = v[1].w;
+        N.w[0] = v[2].x; N.w[1] = v[2].y; N.w[2] = v[2].z; N.w[3] = v[2].w;
+        N.w[4] = v[3].x; N.w[5] = v[3].y; N.w[6] = v[3].z; N.w[7] = v[3].w;
+        sym_apply<SYM>(W, h);
+        sym_apply<SYM>(N, h);
+        v[0] = make_uint4(W.w[0], W.w[1], W.w[2], W.w[3]);
+        v[1] = make_uint4(W.w[4], W.w[5], W.w[6], W.w[7]);
+        v[2] = make_uint4(N.w[0], N.w[1], N.w[2], N.w[3]);
+        v[3] = make_uint4(N.w[4], N.w[5], N.w[6], N.w[7]);
+        quad_transpose(v, ql);  // slot p: piece ql of entry r0 + 16 p + qq
+#pragma unroll
+        for (int p = 0; p < 4; p++) {
+            const int rp = r0 + 16 * p + qq;
+            if (rp < end) J.dst[4 * (size_t)(base + (uint32_t)rp) + ql] = v[p];
+        }
+    }
+}
+
+hipError_t launch_transform(const SymJob &job, const DevTables &T, hipStream_t s)
+{
+    if (job.nchunks == 0) return hipSuccess;
+    const dim3 grid((unsigned)job.nchunks), block(256);
+    switch (job.sym) {
+    case 0: hipLaunchKernelGGL(transform_kernel<0>, grid, block, 0, s, job, T); break;
+    case 1: hipLaunchKernelGGL(transform_kernel<1>, grid, block, 0, s, job, T); break;
+    case 2: hipLaunchKernelGGL(transform_kernel<2>, grid, block, 0, s, job, T); break;
+    case 3: hipLaunchKernelGGL(transform_kernel<3>, grid, block, 0, s, job, T); break;
+    case 4: hipLaunchKernelGGL(transform_kernel<4>, grid, block, 0, s, job, T); break;
+    case 5: hipLaunchKernelGGL(transform_kernel<5>, grid, block, 0, s, job, T); break;
+    case 6: hipLaunchKernelGGL(transform_kernel<6>, grid, block, 0, s, job, T); break;
+    case 7: hipLaunchKernelGGL(transform_kernel<7>, grid, block, 0, s, job, T); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+pentago_section section_image(const pentago_section &s, int sym)
+{
+    pentago_section r;
+    for (int q = 0; q < 4; q++) {
+        r.black[sym_quadrant(sym, q)] = s.black[q];
+        r.white[sym_quadrant(sym, q)] = s.white[q];
+    }
+    return r;
+}
+
+// Lexicographic order of the count tuples ((b0, w0), ..., (b3, w3)).
+static bool section_less(const pentago_section &a, const pentago_section &b)
+{
+    for (int q = 0; q < 4; q++) {
+        if (a.black[q] != b.black[q]) return a.black[q] < b.black[q];
+        if (a.white[q] != b.white[q]) return a.white[q] < b.white[q];
+    }
+    return false;
+}
+
+void section_standardize(const pentago_section &s, pentago_section *rep, int *sym)
+{
+    pentago_section best = s;
+    int bestd = 0;
+    for (int d = 1; d < 8; d++) {
+        const pentago_section img = section_image(s, d);
+        if (section_less(img, best)) {
+            best = img;
+            bestd = d;
+        }
+    }
+    *rep = best;
+    *sym = sym_inverse(bestd);
+}
+
+int make_sym_job(const pentago_section &s, const pentago_superinfo *table, int sym,
+                 pentago_superinfo *out, SymJob *J)
+{
+    if (!section_valid(s)) return fail(PENTAGO_EINVAL, "invalid section counts");
+    if (sym < 0 || sym > 7) return fail(PENTAGO_EINVAL, "symmetry must be 0..7");
+    if (!table || !out) return fail(PENTAGO_EINVAL, "table or out is NULL");
+    const pentago_section img = section_image(s, sym);
+    const HostTables &H = host_tables();
+    memset(J, 0, sizeof(*J));
+    J->sym = sym;
+    section_shape_of(s, J->sm);
+    section_shape_of(img, J->m);
+    uint64_t entries = 1;
+    J->nchunks = 4;
+    for (int j = 0; j < 4; j++) {
+        J->qb[j] = H.class_start[img.black[j]][img.white[j]];
+        J->nb[j] = (J->m[j] + 7) / 8;
+        J->nchunks *= J->nb[j];
+        entries *= (uint64_t)J->m[j];
+    }
+    if (entries >= (1ull << 32)) return fail(PENTAGO_ERANGE, "sections of 2^32 entries or more are not supported");
+    const uintptr_t a = (uintptr_t)table, b = (uintptr_t)out, n = (uintptr_t)(entries * 64);
+    if (a < b + n && b < a + n) return fail(PENTAGO_EINVAL, "out overlaps the source table");
+    J->src = (const uint4 *)table;
+    J->dst = (uint4 *)out;
+    return 0;
+}
+
+}  // namespace pg
+
+using namespace pg;
+
+extern "C" {
+
+int pentago_section_image(pentago_section s, int sym, pentago_section *image)
+{
+    if (!section_valid(s) || sym < 0 || sym > 7 || !image) return fail(PENTAGO_EINVAL, "invalid arguments");
+    *image = section_image(s, sym);
+    return 0;
+}
+
+int pentago_section_standardize(pentago_section s, pentago_section *rep, int *sym)
+{
+    if (!section_valid(s) || !rep || !sym) return fail(PENTAGO_EINVAL, "invalid arguments");
+    section_standardize(s, rep, sym);
+    return 0;
+}
+
+int pentago_section_transform(pentago_section s, const pentago_superinfo *table, int sym,
+                              pentago_superinfo *out, void *hip_stream)
+{
+    DevTables T;
+    int rc = device_tables(&T);
+    if (rc) return rc;
+    SymJob J;
+    rc = make_sym_job(s, table, sym, out, &J);
+    if (rc) return rc;
+    const hipError_t e = launch_transform(J, T, (hipStream_t)hip_stream);
+    return e == hipSuccess ? 0 : hip_fail(e, "transform launch");
+}
+
+int pentago_solve_section_d4(pentago_section s, const pentago_superinfo *const rep[4],
+                             pentago_superinfo *out, void *hip_stream)
+{
+    if (!section_valid(s) || !rep) return fail(PENTAGO_EINVAL, "invalid arguments");
+    DevTables T;
+    int rc = device_tables(&T);
+    if (rc) return rc;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    keep_pool(dev);
+    const hipStream_t st = (hipStream_t)hip_stream;
+    const pentago_superinfo *child[4] = {nullptr, nullptr, nullptr, nullptr};
+    void *scratch[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int j = 0; j < 4 && rc == 0; j++) {
+        if (!rep[j] || s.black[j] + s.white[j] == 9) continue;
+        const pentago_section c = child_of(s, j);
+        pentago_section r;
+        int sym = 0;
+        section_standardize(c, &r, &sym);
+        if (sym == 0) {
+            child[j] = rep[j];
+            continue;
+        }
+        int m[4];
+        section_shape_of(c, m);
+        const size_t bytes = (size_t)m[0] * m[1] * m[2] * m[3] * sizeof(pentago_superinfo);
+        e = hipMallocAsync(&scratch[j], bytes, st);
+        if (e != hipSuccess) {
+            scratch[j] = nullptr;
+            rc = hip_fail(e, "hipMallocAsync(child image)");
+            break;
+        }
+        SymJob SJ;
+        rc = make_sym_job(r, rep[j], sym, (pentago_superinfo *)scratch[j], &SJ);
+        if (rc == 0) {
+            e = launch_transform(SJ, T, st);
+            if (e != hipSuccess) rc = hip_fail(e, "transform launch");
+        }
+        child[j] = (const pentago_superinfo *)scratch[j];
+    }
+    if (rc == 0) {
+        SweepJob J;
+        rc = make_job(s, child, out, &J, -1, 0);
+        if (rc == 0) rc = run_job(J, T, st);
+    }
+    for (int j = 0; j < 4; j++)
+        if (scratch[j]) (void)hipFreeAsync(scratch[j], st);
+    return rc;
+}
+
+}  // extern "C"

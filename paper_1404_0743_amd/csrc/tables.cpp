@@ -1,6 +1,8 @@
 // tables.cpp -- construction of the host-side quadrant and DAG tables.
 #include "tables.h"
 
+#include <stdexcept>
+
 #include <algorithm>
 #include <mutex>
 
@@ -26,6 +28,9 @@ static int turn_cell(int l)
     const int lr = l / 3, lc = l % 3;
     return 3 * (2 - lc) + lr;
 }
+
+// local cell after the left-right mirror: (lr, lc) -> (lr, 2 - lc)
+static int mirror_cell(int l) { return 3 * (l / 3) + 2 - l % 3; }
 
 static unsigned turn_mask(unsigned m, int k)
 {
@@ -180,6 +185,47 @@ static void build_line_structure(HostTables &t)
     }
 }
 
+// Pattern maps of the 8 board symmetries (see HostTables::symmap).  With
+// lam the local map of symmetry sym, an image pattern c' comes from the
+// source pattern c = canonical form of lam^-1(c'); lam(c) is c' turned by
+// some h, read off the canonicalising turn count of lam(c).
+static void build_symmetry(HostTables &t)
+{
+    const int NC = 19683;
+    std::vector<uint16_t> mirror1(NC);
+    for (int code = 0; code < NC; code++) {
+        int r = 0;
+        for (int l = 0; l < 9; l++) r += (code / pow3(l)) % 3 * pow3(mirror_cell(l));
+        mirror1[code] = (uint16_t)r;
+    }
+    auto turns = [&](int code, int k) {
+        for (int i = 0; i < (k & 3); i++) code = t.turn1[code];
+        return code;
+    };
+    t.symmap.assign(8 * kPatterns, 0);
+    for (int sym = 0; sym < 8; sym++) {
+        const int r = sym & 3;
+        const bool f = (sym & 4) != 0;
+        for (int b = 0; b <= 9; b++)
+            for (int w = 0; b + w <= 9; w++) {
+                const int start = t.class_start[b][w];
+                for (int i = 0; i < t.class_size[b][w]; i++) {
+                    const int img = t.qinfo[start + i].code;
+                    int x = turns(img, 4 - r);          // lam^-1 = mirror^f . turn^-r
+                    if (f) x = mirror1[x];
+                    const int src = t.canon[x] & 0xfff;
+                    int y = t.qinfo[start + src].code;  // lam(c) = turn^r . mirror^f (c)
+                    if (f) y = mirror1[y];
+                    y = turns(y, r);
+                    // y turned by K (its canonicalising count) is c', so y = c' turned -K
+                    const int K = t.canon[y] >> 12;
+                    if ((t.canon[y] & 0xfff) != i) throw std::logic_error("symmetry map");
+                    t.symmap[sym * kPatterns + start + i] = (uint16_t)(src | (((4 - K) & 3) << 12));
+                }
+            }
+    }
+}
+
 static void build(HostTables &t)
 {
     const int NC = 19683;
@@ -222,6 +268,7 @@ static void build(HostTables &t)
     t.canon.resize(NC);
     for (int code = 0; code < NC; code++)
         t.canon[code] = (uint16_t)(index[minc[code]] | (mink[code] << 12));
+    build_symmetry(t);
     build_line_masks(t);
     build_line_structure(t);
 }

@@ -10,6 +10,9 @@
 
 namespace pg {
 
+// Rotation-minimal quadrant patterns over all (black, white) classes.
+constexpr int kPatterns = 4995;
+
 // One rotation-minimal quadrant pattern.
 struct QInfo {
     uint16_t code;   // ternary code, digit 0 empty / 1 black / 2 white at 3^local
@@ -26,6 +29,16 @@ struct HostTables {
                                   // its class representative
     std::vector<uint16_t> turn1;  // per code: code after one counter-clockwise turn
     std::vector<LineMasks> lm;    // [quadrant * 512 + stone mask]
+
+    // Board symmetries (Section III: the group G of approximate symmetries
+    // contains the 8 board symmetries, which move each quadrant onto a
+    // quadrant, sym_quadrant in set256.h, and act on its nine cells by one
+    // local map: a mirror when the symmetry is a reflection, then sym & 3
+    // counter-clockwise turns).  symmap[sym * kPatterns + i], for pattern i
+    // (qinfo order) of an image section: the index, within the same class, of
+    // the source pattern whose local image is a turn of pattern i, | h << 12,
+    // where that local image is pattern i turned h more times (h = 0..3).
+    std::vector<uint16_t> symmap;  // [8 * kPatterns]
 
     // Line structure used by the sweep (five_lut in sweep.hip):
     // sel[(j * 512 + m) * 4 + k] describes the lines through quadrant j that

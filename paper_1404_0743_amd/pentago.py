@@ -66,6 +66,10 @@ _SIGS = {
     "pentago_section_board": ([Section, _P, _P], ctypes.c_int),
     "pentago_child_section": ([Section, ctypes.c_int, _P], ctypes.c_int),
     "pentago_solve_section": ([Section, _P, _P, _P], ctypes.c_int),
+    "pentago_section_image": ([Section, ctypes.c_int, _P], ctypes.c_int),
+    "pentago_section_standardize": ([Section, _P, _P], ctypes.c_int),
+    "pentago_section_transform": ([Section, _P, ctypes.c_int, _P, _P], ctypes.c_int),
+    "pentago_solve_section_d4": ([Section, _P, _P, _P], ctypes.c_int),
     "pentago_solve_sections": ([_P, ctypes.c_size_t, _P], ctypes.c_int),
     "pentago_autotune_section": ([Section, _P, _P, _P, _P, _P], ctypes.c_int),
     "pentago_solve_section_shape": ([Section, _P, _P, _P, _P], ctypes.c_int),
@@ -90,6 +94,9 @@ _SIGS = {
     "pentago_debug_rmax": ([_P, _P], ctypes.c_int),
     "pentago_debug_shift": ([_P, ctypes.c_int, ctypes.c_int, _P], ctypes.c_int),
     "pentago_debug_canon": ([ctypes.c_int, _P, _P], ctypes.c_int),
+    "pentago_debug_sym": ([_P, ctypes.c_int, _P, _P], ctypes.c_int),
+    "pentago_debug_sym_pattern": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P],
+                                  ctypes.c_int),
     "pentago_debug_swap3": ([_P, ctypes.c_int, _P], ctypes.c_int),
 }
 
@@ -198,6 +205,34 @@ def pentago_child_section(counts, j):
     return tuple((c.black[k], c.white[k]) for k in range(4))
 
 
+# ---------------------------------------------------------------- board symmetries
+
+def _counts_of(sec):
+    return tuple((sec.black[k], sec.white[k]) for k in range(4))
+
+
+def pentago_section_image(counts, sym):
+    """Counts of the image section under board symmetry sym (0..7)."""
+    c = Section()
+    _check(lib().pentago_section_image(section(counts), int(sym), ctypes.byref(c)), "pentago_section_image")
+    return _counts_of(c)
+
+
+def pentago_section_standardize(counts):
+    """(representative counts, sym) with pentago_section_image(rep, sym) == counts."""
+    c = Section()
+    sym = ctypes.c_int()
+    _check(lib().pentago_section_standardize(section(counts), ctypes.byref(c), ctypes.byref(sym)),
+           "pentago_section_standardize")
+    return _counts_of(c), sym.value
+
+
+def pentago_section_transform(counts, table, sym, out, stream=None):
+    """out (device, entries x 64 B) = the table of pentago_section_image(counts, sym)."""
+    _check(lib().pentago_section_transform(section(counts), _dev_ptr(table), int(sym), _dev_ptr(out),
+                                           _stream(stream)), "pentago_section_transform")
+
+
 # ---------------------------------------------------------------- sweep
 
 def pentago_solve_section(counts, children, out, stream=None):
@@ -208,6 +243,14 @@ def pentago_solve_section(counts, children, out, stream=None):
             _dev_ptr(c)
     _check(lib().pentago_solve_section(section(counts), ch, _dev_ptr(out), _stream(stream)),
            "pentago_solve_section")
+
+
+def pentago_solve_section_d4(counts, reps, out, stream=None):
+    """reps: 4 device tensors holding the tables of the children's
+    representatives (pentago_section_standardize), or None."""
+    ch = (ctypes.c_void_p * 4)(*[None if c is None else _dev_ptr(c) for c in reps])
+    _check(lib().pentago_solve_section_d4(section(counts), ch, _dev_ptr(out), _stream(stream)),
+           "pentago_solve_section_d4")
 
 
 def pentago_autotune_section(counts, children, out, stream=None):
@@ -388,6 +431,22 @@ def pentago_debug_swap3(words, d):
     src, out = _set(words), Set256()
     _check(lib().pentago_debug_swap3(ctypes.byref(src), d, ctypes.byref(out)), "pentago_debug_swap3")
     return np.array(out.w, dtype=np.uint64)
+
+
+def pentago_debug_sym(words, sym, h):
+    """words: 4 u64 (bit g in word g >> 6); h: turns of the 4 image quadrants."""
+    src, out = _set(words), Set256()
+    hh = (ctypes.c_int * 4)(*[int(x) for x in h])
+    _check(lib().pentago_debug_sym(ctypes.byref(src), int(sym), hh, ctypes.byref(out)), "pentago_debug_sym")
+    return np.array(out.w, dtype=np.uint64)
+
+
+def pentago_debug_sym_pattern(sym, black, white, index):
+    src = ctypes.c_int()
+    h = ctypes.c_int()
+    _check(lib().pentago_debug_sym_pattern(int(sym), int(black), int(white), int(index), ctypes.byref(src),
+                                           ctypes.byref(h)), "pentago_debug_sym_pattern")
+    return src.value, h.value
 
 
 def pentago_debug_canon(code):
