@@ -10,7 +10,7 @@ Prints one JSON line: throughput in positions/s, the roofline of the sweep
 kernel (algorithmic bytes over HIP-event time on the launch stream) and the
 CPU oracle timed on a bounded sample of the same section.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra] [--extra a,b]
 """
 import argparse
 import json
@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other workloads (endgame batches, uneven layers)")
+    ap.add_argument("--extra", default=None,
+                    help="comma-separated subset of the other workloads to run (default: all)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 512 MiB fill and a 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -96,8 +98,17 @@ def main():
               "is not implemented", file=sys.stderr)
         sys.exit(2)
 
+    only = None
+    if args.extra:
+        import bench_extra
+        only = set(args.extra.split(","))
+        unknown = only - set(bench_extra.NAMES)
+        if unknown:
+            print("unknown workloads: %s (known: %s)" % (sorted(unknown), ", ".join(bench_extra.NAMES)),
+                  file=sys.stderr)
+            sys.exit(2)
     boards_2p20 = serve_queries = None
-    if not args.no_extra:
+    if not args.no_extra and (only is None or only & {"endgame_2p20", "serving", "serving_resident"}):
         # generated before the GPU is touched (the generator forks workers)
         from paper_1404_0743_amd import inputs as I
         t0 = time.perf_counter()
@@ -195,7 +206,7 @@ def main():
         import bench_extra
         out_keep, child_keep = out, child
         resident = [(SECTION, out_keep), (CHILD, child_keep)]
-        res["extra"] = bench_extra.run_all(P, torch, stream, boards_2p20, serve_queries, resident)
+        res["extra"] = bench_extra.run_all(P, torch, stream, boards_2p20, serve_queries, resident, only)
     if not args.no_cpu:
         log("timing the CPU oracle on a sample ...")
         res["cpu_baseline"] = cpu_baseline(entries, positions)

@@ -17,6 +17,10 @@
                  2^16 queries drawn from the resident sections (random
                  quadrant turns), answered by lookup: alone, and mixed one to
                  one with random-play queries under Poisson arrivals.
+  symmetry       the table transform under each of the 7 non-trivial board
+                 symmetries of the 36->35 section (6,288,640 entries), and
+                 sweeps whose child is held only as its D4 representative
+                 (pentago_solve_section_d4) against the plain sweep.
 Inputs are resident on the GPU when timing starts; times are HIP events on
 the launch stream.
 """
@@ -247,13 +251,60 @@ def serving_resident(P, torch, stream, resident, queries):
     return out
 
 
-def run_all(P, torch, stream, boards_2p20=None, serve_queries=None, resident=None):
+def symmetry(P, torch, stream, resident):
+    """Transform of the resident 36->35 section under each board symmetry
+    (algorithmic bytes: 64 B read + 64 B written per entry), and sweeps over
+    representatives against plain sweeps of the same sections."""
+    src_counts, src = resident[0]
+    n = src.shape[0]
+    out = torch.empty_like(src)
+    res = {"section": str(src_counts), "entries": n, "transform": {}}
+    for sym in range(1, 8):
+        med, mn = _time(torch, stream, lambda: P.pentago_section_transform(src_counts, src, sym, out, stream), 10)
+        gbs = 128 * n / (med * 1e-3) / 1e9
+        res["transform"][str(sym)] = {"ms": med, "min_ms": mn, "GB_s": gbs, "frac_hbm": gbs / 8000.0}
+    fr = [v["frac_hbm"] for v in res["transform"].values()]
+    res["transform_frac_hbm_mean"] = float(np.mean(fr))
+    del out
+    res["sweep_d4"] = []
+    for counts in (((5, 4), (4, 5), (5, 4), (4, 4)), ((4, 4), (4, 5), (6, 3), (4, 5))):
+        j = [k for k in range(4) if sum(counts[k]) < 9][0]
+        child = P.pentago_child_section(counts, j)
+        rep, sym = P.pentago_section_standardize(child)
+        _, ce, _ = P.pentago_section_shape(child)
+        _, e, pos = P.pentago_section_shape(counts)
+        ct = torch.empty((ce, 8), dtype=torch.int64, device="cuda")
+        rt = torch.empty((ce, 8), dtype=torch.int64, device="cuda")
+        P.pentago_solve_section(child, [None] * 4, ct, stream)
+        P.pentago_solve_section(rep, [None] * 4, rt, stream)
+        kids, reps = [None] * 4, [None] * 4
+        kids[j], reps[j] = ct, rt
+        a = torch.empty((e, 8), dtype=torch.int64, device="cuda")
+        b = torch.empty((e, 8), dtype=torch.int64, device="cuda")
+        P.pentago_autotune_section(counts, kids, a, stream)
+        t_plain, _ = _time(torch, stream, lambda: P.pentago_solve_section(counts, kids, a, stream), 10)
+        t_d4, _ = _time(torch, stream, lambda: P.pentago_solve_section_d4(counts, reps, b, stream), 10)
+        res["sweep_d4"].append({"section": str(counts), "child": str(child), "child_rep": str(rep),
+                                "child_sym": sym, "positions": pos, "plain_ms": t_plain, "d4_ms": t_d4,
+                                "d4_positions_per_s": pos / (t_d4 * 1e-3), "bit_exact": bool(torch.equal(a, b))})
+        del a, b, ct, rt
+    torch.cuda.empty_cache()
+    return res
+
+
+NAMES = ("endgame_4096", "endgame_2p20", "layers", "serving", "serving_resident", "symmetry")
+
+
+def run_all(P, torch, stream, boards_2p20=None, serve_queries=None, resident=None, only=None):
     res = {}
     for name, fn in (("endgame_4096", lambda: endgame(P, torch, stream, I.random_placement_boards(4096, 17, 16), False)),
                      ("endgame_2p20", lambda: endgame(P, torch, stream, boards_2p20, True)),
                      ("layers", lambda: layers(P, torch, stream, resident)),
                      ("serving", lambda: serving(P, torch, stream, resident, serve_queries)),
-                     ("serving_resident", lambda: serving_resident(P, torch, stream, resident, serve_queries))):
+                     ("serving_resident", lambda: serving_resident(P, torch, stream, resident, serve_queries)),
+                     ("symmetry", lambda: symmetry(P, torch, stream, resident))):
+        if only is not None and name not in only:
+            continue
         if name == "endgame_2p20" and boards_2p20 is None:
             continue
         if name.startswith("serving") and serve_queries is None:

@@ -39,7 +39,8 @@ struct SymJob {
     int sm[4];          // source shape
     int qb[4];          // first QInfo index of each image quadrant class
     int nb[4];          // blocks of the image per dimension
-    long long nchunks;  // image blocks x 4 quarters
+    long long nblocks;  // image blocks
+    long long nchunks;  // workgroups: 4 quarters of each block, blocks padded to a multiple of 8
     const uint4 *src;
     uint4 *dst;
 };

@@ -12,17 +12,31 @@
 namespace pg {
 
 // One workgroup takes a quarter of one 8^4 block of the image section (up to
-// 1024 entries; each wave 64 neighbouring entries per step).  The entries of
-// an image block are contiguous in the image table.  Lane i works on entry
-// 16 (i & 3) + (i >> 2) of its wave's 64: it finds its source entry (one
-// source block for a rotation, a few for a reflection, which reorders the
-// patterns inside each dimension), the quad loads its four source entries
-// whole, transposes, transforms, transposes back and stores 1 KB runs.
+// 1024 entries; each wave 64 entries per step).  The block's entries are
+// enumerated with image dimension 3 fastest and next the image dimension A
+// that receives the source's dimension 3 (for symmetries that keep
+// dimension 3 in place, dimension 2): so the two entries of a 128-byte
+// source line, neighbours along source dimension 3, are read in the same
+// step (for the rotations; a reflection also reorders the patterns inside
+// each dimension, and can separate them), while each store instruction
+// still writes runs of eight neighbouring image entries.  Lane i works on
+// entry 16 (i & 3) + (i >> 2) of its wave's 64: it finds its source entry,
+// the quad loads its four source entries whole, transposes, transforms,
+// transposes back and stores its four image entries whole.
 template <int SYM>
 __global__ void __launch_bounds__(256) transform_kernel(SymJob J, DevTables T)
 {
-    long long blk = (long long)blockIdx.x >> 2;
-    const int quarter = (int)(blockIdx.x & 3u);
+    // Workgroups reach the 8 XCDs in turn (workgroup b on XCD b mod 8): the
+    // four quarters of image block 8 k + x run on XCD x one after another.
+    const uint32_t x = blockIdx.x & 7u, k = blockIdx.x >> 3;
+    long long blk = (long long)(k >> 2) * 8 + x;
+    const int quarter = (int)(k & 3u);
+    if (blk >= J.nblocks) return;
+    // enumeration order of the block's dimensions, slowest first
+    constexpr int A = sym_quadrant(SYM, 3) == 3 ? 2 : sym_quadrant(SYM, 3);
+    constexpr int O1 = A == 0 ? 1 : 0;
+    constexpr int O2 = (A == 2 || O1 == 2) ? (A == 1 || O1 == 1 ? 0 : 1) : 2;
+    constexpr int D0 = O1 < O2 ? O1 : O2, D1 = O1 < O2 ? O2 : O1;
     int corner[4], s[4];
     {
         int B[4];
@@ -41,7 +55,7 @@ __global__ void __launch_bounds__(256) transform_kernel(SymJob J, DevTables T)
     const int end = min(vol, 1024 * (quarter + 1));
     // r / s for r < 4096 and s <= 8 as a multiply-high by ceil(2^16 / s):
     // the error stays below 1/16, under the 1/s gap to the next integer
-    const uint32_t mg1 = (65535u + s[1]) / s[1], mg2 = (65535u + s[2]) / s[2],
+    const uint32_t mg1 = (65535u + s[D1]) / s[D1], mg2 = (65535u + s[A]) / s[A],
                    mg3 = (65535u + s[3]) / s[3];
     const uint16_t *map = T.symmap + SYM * kPatterns;
     const int ql = (int)(threadIdx.x & 3u), qq = (int)((threadIdx.x & 63u) >> 2);
@@ -51,7 +65,11 @@ __global__ void __launch_bounds__(256) transform_kernel(SymJob J, DevTables T)
         const uint32_t q3 = ((uint32_t)r * mg3) >> 16;
         const uint32_t q2 = (q3 * mg2) >> 16;
         const uint32_t q1 = (q2 * mg1) >> 16;
-        const int loc[4] = {(int)q1, (int)(q2 - q1 * s[1]), (int)(q3 - q2 * s[2]), (int)(r - q3 * s[3])};
+        int loc[4];
+        loc[D0] = (int)q1;
+        loc[D1] = (int)(q2 - q1 * s[D1]);
+        loc[A] = (int)(q3 - q2 * s[A]);
+        loc[3] = (int)(r - q3 * s[3]);
         int sidx[4], h[4];
 #pragma unroll
         for (int j = 0; j < 4; j++) {
@@ -59,6 +77,7 @@ __global__ void __launch_bounds__(256) transform_kernel(SymJob J, DevTables T)
             h[j] = (int)(e >> 12);
             sidx[sym_source(SYM, j)] = (int)(e & 0xfffu);
         }
+        const uint32_t doff = base + (uint32_t)(((loc[0] * s[1] + loc[1]) * s[2] + loc[2]) * s[3] + loc[3]);
         const uint32_t off = block_offset(J.sm, sidx);
         const uint32_t offs[4] = {quad_perm<0x00>(off), quad_perm<0x55>(off), quad_perm<0xAA>(off),
                                   quad_perm<0xFF>(off)};
@@ -77,12 +96,12 @@ __global__ void __launch_bounds__(256) transform_kernel(SymJob J, DevTables T)
         v[1] = make_uint4(W.w[4], W.w[5], W.w[6], W.w[7]);
         v[2] = make_uint4(N.w[0], N.w[1], N.w[2], N.w[3]);
         v[3] = make_uint4(N.w[4], N.w[5], N.w[6], N.w[7]);
-        quad_transpose(v, ql);  // slot p: piece ql of entry r0 + 16 p + qq
+        quad_transpose(v, ql);  // slot p: piece ql of the entry of quad lane p
+        const uint32_t doffs[4] = {quad_perm<0x00>(doff), quad_perm<0x55>(doff), quad_perm<0xAA>(doff),
+                                   quad_perm<0xFF>(doff)};
 #pragma unroll
-        for (int p = 0; p < 4; p++) {
-            const int rp = r0 + 16 * p + qq;
-            if (rp < end) J.dst[4 * (size_t)(base + (uint32_t)rp) + ql] = v[p];
-        }
+        for (int p = 0; p < 4; p++)
+            if (r0 + 16 * p + qq < end) J.dst[4 * (size_t)doffs[p] + ql] = v[p];
     }
 }
 
@@ -152,13 +171,14 @@ int make_sym_job(const pentago_section &s, const pentago_superinfo *table, int s
     section_shape_of(s, J->sm);
     section_shape_of(img, J->m);
     uint64_t entries = 1;
-    J->nchunks = 4;
+    J->nblocks = 1;
     for (int j = 0; j < 4; j++) {
         J->qb[j] = H.class_start[img.black[j]][img.white[j]];
         J->nb[j] = (J->m[j] + 7) / 8;
-        J->nchunks *= J->nb[j];
+        J->nblocks *= J->nb[j];
         entries *= (uint64_t)J->m[j];
     }
+    J->nchunks = 4 * 8 * ((J->nblocks + 7) / 8);
     if (entries >= (1ull << 32)) return fail(PENTAGO_ERANGE, "sections of 2^32 entries or more are not supported");
     const uintptr_t a = (uintptr_t)table, b = (uintptr_t)out, n = (uintptr_t)(entries * 64);
     if (a < b + n && b < a + n) return fail(PENTAGO_EINVAL, "out overlaps the source table");
