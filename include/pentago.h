@@ -157,14 +157,12 @@ int pentago_solve_section(pentago_section s, const pentago_superinfo *const chil
  *   rep[j]  device table of the representative of pentago_child_section(s, j)
  *           (pentago_section_standardize), or NULL when quadrant j is full or
  *           its child is a 36-stone section evaluated on demand.
- *   out     as in pentago_solve_section.
- * A child that is its own representative is read in place; any other child
- * is first rebuilt from its representative by pentago_section_transform into
- * scratch memory allocated stream-ordered on hip_stream (hipMallocAsync) and
- * released after the sweep, so the call needs that much device memory free.
- * The result is bit for bit the pentago_solve_section result with the
- * children themselves.  Errors as pentago_solve_section, plus EDEVICE when
- * the scratch allocation fails. */
+ *   out     as in pentago_solve_section; must not overlap any rep[j].
+ * Each child entry the sweep needs is read from the representative's table
+ * and transformed in registers as pentago_section_transform would (no
+ * scratch memory, no extra pass).  The result is bit for bit the
+ * pentago_solve_section result with the children themselves.  Errors as
+ * pentago_solve_section. */
 int pentago_solve_section_d4(pentago_section s, const pentago_superinfo *const rep[4],
                              pentago_superinfo *out, void *hip_stream);
 

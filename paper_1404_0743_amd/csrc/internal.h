@@ -36,8 +36,6 @@ pentago_section section_image(const pentago_section &s, int sym);
 void section_standardize(const pentago_section &s, pentago_section *rep, int *sym);
 int make_sym_job(const pentago_section &s, const pentago_superinfo *table, int sym,
                  pentago_superinfo *out, SymJob *J);
-// Keep the device's stream-ordered allocations pooled (hipMallocAsync).
-void keep_pool(int dev);
 int eval_grid(int *grid);
 size_t eval_scratch_bytes(size_t n, int grid, bool deep);
 int eval_enqueue(const uint64_t *boards, size_t n, uint4 *out, int *status, bool deep, int grid,

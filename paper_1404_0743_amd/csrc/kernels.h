@@ -69,6 +69,14 @@ struct SweepJob {
     int lds_bytes;     // dynamic LDS needed by one tile
     int threads;       // workgroup size of the one-section sweep (256 or 512)
     int order;         // tile order of the one-section sweep (0 natural, 1 by XCD)
+    // Children held as their representatives under the board symmetries:
+    // child[j] is then the table of a section whose image under symmetry
+    // csym[j] is child j (0: child[j] is child j itself); rm[j] is that
+    // section's shape and rsrc[j][k] its dimension that child dimension k
+    // comes from.
+    int csym[4];
+    int rm[4][4];
+    int rsrc[4][4];
 };
 
 // Host launchers (sweep.hip, endgame.hip, symmetry.hip).

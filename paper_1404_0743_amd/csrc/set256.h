@@ -316,6 +316,21 @@ PG_HD void sym_apply(Set256 &x, const int h[4])
     x = shift_dim(x, 3, h[3]);
 }
 
+// Both sets of an entry (win, not-lose) under one runtime symmetry.
+PG_HD void sym_apply_rt2(Set256 &a, Set256 &b, int sym, const int h[4])
+{
+    switch (sym & 7) {
+    case 0: sym_apply<0>(a, h); sym_apply<0>(b, h); break;
+    case 1: sym_apply<1>(a, h); sym_apply<1>(b, h); break;
+    case 2: sym_apply<2>(a, h); sym_apply<2>(b, h); break;
+    case 3: sym_apply<3>(a, h); sym_apply<3>(b, h); break;
+    case 4: sym_apply<4>(a, h); sym_apply<4>(b, h); break;
+    case 5: sym_apply<5>(a, h); sym_apply<5>(b, h); break;
+    case 6: sym_apply<6>(a, h); sym_apply<6>(b, h); break;
+    default: sym_apply<7>(a, h); sym_apply<7>(b, h); break;
+    }
+}
+
 PG_HD void sym_apply_rt(Set256 &x, int sym, const int h[4])
 {
     switch (sym & 7) {

@@ -20,6 +20,31 @@ __device__ __forceinline__ int get4(const Idx4 &x, int j)
     return j == 0 ? x.v[0] : j == 1 ? x.v[1] : j == 2 ? x.v[2] : x.v[3];
 }
 
+// Entry idx of child JD when the child is held as its representative under
+// board symmetry J.csym[JD] (Section III: the table of an image is the
+// representative's with dimensions moved, reflected for a reflection, and
+// shifted): the representative's entry, and in h the turns that complete
+// the transform (sym_apply).
+template <int JD>
+__device__ __forceinline__ const uint4 *child_rep_entry(const SweepJob &J, const DevTables &T, const int *idx,
+                                                      int h[4])
+{
+    const uint16_t *map = T.symmap + J.csym[JD] * kPatterns;
+    uint32_t e[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        e[k] = map[(k == JD ? J.cqb[k] : J.qb[k]) + idx[k]];
+        h[k] = (int)(e[k] >> 12);
+        e[k] &= 0xfffu;
+    }
+    const int *src = J.rsrc[JD];
+    int sidx[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+        sidx[t] = (int)(src[0] == t ? e[0] : src[1] == t ? e[1] : src[2] == t ? e[2] : e[3]);
+    return J.child[JD] + 4 * block_offset(J.rm[JD], sidx);
+}
+
 // A child entry's contribution, prepared once per child entry of a staged
 // line and used by every parent of the line that reaches it (Section III:
 // rmax is translation invariant, so it commutes with the canonicalising
@@ -50,9 +75,15 @@ __device__ __forceinline__ void child_entry_terms(const SweepJob &J, const DevTa
             N.w[i] = Fo.w[i] | ~Fc.w[i];
         }
     } else {
-        int cshape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
-        cshape[JD] = J.cm[JD];
-        load_info(J.child[JD] + 4 * block_offset(cshape, idx.v), W, N);
+        if (J.csym[JD]) {
+            int h[4];
+            load_info(child_rep_entry<JD>(J, T, idx.v, h), W, N);
+            sym_apply_rt2(W, N, J.csym[JD], h);
+        } else {
+            int cshape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
+            cshape[JD] = J.cm[JD];
+            load_info(J.child[JD] + 4 * block_offset(cshape, idx.v), W, N);
+        }
     }
     const Set256 Fc = board_five(T, cm_);
     child_terms(Fc, W, N, A, B);
@@ -298,7 +329,8 @@ int sweep_lds_bytes(int G, int mD, int cmD)
     return tile_lds_bytes(G, mD, cmD, nullptr, nullptr);
 }
 
-template <int D>
+// SYMC: the staged child is held as its representative (J.csym[D] != 0).
+template <int D, bool SYMC = false>
 __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile, void *lds_base)
 {
     // tile = ((i_O1 * m_O2) + i_O2) * ngroups + group of G lines along E
@@ -331,13 +363,14 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
     // The first child item of this thread is fetched from HBM now, so its
     // latency overlaps the table set-up below.
     uint4 pre[4] = {};
+    int hpre[4] = {0, 0, 0, 0};
     if (load_children && (int)threadIdx.x < nlines * cmD) {
         const int it = threadIdx.x;
         const int ic = (int)(((uint32_t)it * rcp) >> 16);
         Idx4 idx = base;
         idx.v[E] = base.v[E] + (it - ic * nlines);
         idx.v[D] = ic;
-        const uint4 *p = J.child[D] + 4 * block_offset(cshape, idx.v);
+        const uint4 *p = SYMC ? child_rep_entry<D>(J, T, idx.v, hpre) : J.child[D] + 4 * block_offset(cshape, idx.v);
 #pragma unroll
         for (int i = 0; i < 4; i++) pre[i] = p[i];
     }
@@ -463,21 +496,39 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
                 *(uint2 *)(r + 8 + i) = make_uint2(B.w[i], B.w[i + 1]);
             }
         };
-        // the first item of each thread uses the prefetched entry
-        if ((int)threadIdx.x < total) child_item(threadIdx.x, set_from(pre), set_from(pre + 2));
-        for (int it = threadIdx.x + blockDim.x; it < total; it += blockDim.x) {
-            Set256 W, N;
-            if (load_children) {
-                const int ic = (int)(((uint32_t)it * rcp) >> 16);
-                Idx4 idx = base;
-                idx.v[E] = base.v[E] + (it - ic * nlines);
-                idx.v[D] = ic;
-                load_info(J.child[D] + 4 * block_offset(cshape, idx.v), W, N);
-            } else {
-                W = s_zero();
-                N = s_zero();
+        if constexpr (SYMC) {
+            // one call site of the transform: the first item of each thread
+            // takes the prefetched representative entry, later items load
+            for (int it = threadIdx.x; it < total; it += blockDim.x) {
+                Set256 W = set_from(pre), N = set_from(pre + 2);
+                int h[4] = {hpre[0], hpre[1], hpre[2], hpre[3]};
+                if (it != (int)threadIdx.x) {
+                    const int ic = (int)(((uint32_t)it * rcp) >> 16);
+                    Idx4 idx = base;
+                    idx.v[E] = base.v[E] + (it - ic * nlines);
+                    idx.v[D] = ic;
+                    load_info(child_rep_entry<D>(J, T, idx.v, h), W, N);
+                }
+                sym_apply_rt2(W, N, J.csym[D], h);
+                child_item(it, W, N);
             }
-            child_item(it, W, N);
+        } else {
+            // the first item of each thread uses the prefetched entry
+            if ((int)threadIdx.x < total) child_item(threadIdx.x, set_from(pre), set_from(pre + 2));
+            for (int it = threadIdx.x + blockDim.x; it < total; it += blockDim.x) {
+                Set256 W, N;
+                if (load_children) {
+                    const int ic = (int)(((uint32_t)it * rcp) >> 16);
+                    Idx4 idx = base;
+                    idx.v[E] = base.v[E] + (it - ic * nlines);
+                    idx.v[D] = ic;
+                    load_info(J.child[D] + 4 * block_offset(cshape, idx.v), W, N);
+                } else {
+                    W = s_zero();
+                    N = s_zero();
+                }
+                child_item(it, W, N);
+            }
         }
         __syncthreads();
     }
@@ -551,8 +602,8 @@ __device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile
     }
 }
 
-template <int D, int NT>
-__global__ void __launch_bounds__(NT, NT == 512 ? 6 : 1) sweep_kernel(SweepJob J, DevTables T)
+template <int D, int NT, bool SYMC = false>
+__global__ void __launch_bounds__(NT, NT == 512 ? (SYMC ? 5 : 6) : 1) sweep_kernel(SweepJob J, DevTables T)
 {
     extern __shared__ uint4 lds[];
     uint32_t tile = blockIdx.x;
@@ -562,7 +613,7 @@ __global__ void __launch_bounds__(NT, NT == 512 ? 6 : 1) sweep_kernel(SweepJob J
         const uint32_t n = (uint32_t)J.ntiles, per = n >> 3, rem = n & 7u, x = tile & 7u;
         tile = x * per + min(x, rem) + (tile >> 3);
     }
-    sweep_tile<D>(J, T, tile, (void *)lds);
+    sweep_tile<D, SYMC>(J, T, tile, (void *)lds);
 }
 
 // Many sections in one persistent launch: workgroups take tiles from a
@@ -618,6 +669,28 @@ hipError_t launch_sweep(const SweepJob &job, const DevTables &T, hipStream_t s)
 {
     if (job.ntiles == 0) return hipSuccess;
     const dim3 grid((unsigned)job.ntiles), block(job.threads);
+    const bool symc = job.csym[job.d & 3] != 0 && ((job.emask >> job.d) & 1) && !((job.odmask >> job.d) & 1);
+    if (symc) {
+        // the staged child read through a board symmetry
+        if (job.threads == 512) {
+            switch (job.d) {
+            case 0: hipLaunchKernelGGL((sweep_kernel<0, 512, true>), grid, block, job.lds_bytes, s, job, T); break;
+            case 1: hipLaunchKernelGGL((sweep_kernel<1, 512, true>), grid, block, job.lds_bytes, s, job, T); break;
+            case 2: hipLaunchKernelGGL((sweep_kernel<2, 512, true>), grid, block, job.lds_bytes, s, job, T); break;
+            default: hipLaunchKernelGGL((sweep_kernel<3, 512, true>), grid, block, job.lds_bytes, s, job, T); break;
+            }
+        } else if (job.threads == 256) {
+            switch (job.d) {
+            case 0: hipLaunchKernelGGL((sweep_kernel<0, 256, true>), grid, block, job.lds_bytes, s, job, T); break;
+            case 1: hipLaunchKernelGGL((sweep_kernel<1, 256, true>), grid, block, job.lds_bytes, s, job, T); break;
+            case 2: hipLaunchKernelGGL((sweep_kernel<2, 256, true>), grid, block, job.lds_bytes, s, job, T); break;
+            default: hipLaunchKernelGGL((sweep_kernel<3, 256, true>), grid, block, job.lds_bytes, s, job, T); break;
+            }
+        } else {
+            return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (job.threads == 512) {
         switch (job.d) {
         case 0: hipLaunchKernelGGL((sweep_kernel<0, 512>), grid, block, job.lds_bytes, s, job, T); break;

@@ -227,48 +227,19 @@ int pentago_solve_section_d4(pentago_section s, const pentago_superinfo *const r
     DevTables T;
     int rc = device_tables(&T);
     if (rc) return rc;
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    keep_pool(dev);
-    const hipStream_t st = (hipStream_t)hip_stream;
-    const pentago_superinfo *child[4] = {nullptr, nullptr, nullptr, nullptr};
-    void *scratch[4] = {nullptr, nullptr, nullptr, nullptr};
-    for (int j = 0; j < 4 && rc == 0; j++) {
+    SweepJob J;
+    rc = make_job(s, rep, out, &J, -1, 0);
+    if (rc) return rc;
+    for (int j = 0; j < 4; j++) {
         if (!rep[j] || s.black[j] + s.white[j] == 9) continue;
-        const pentago_section c = child_of(s, j);
         pentago_section r;
         int sym = 0;
-        section_standardize(c, &r, &sym);
-        if (sym == 0) {
-            child[j] = rep[j];
-            continue;
-        }
-        int m[4];
-        section_shape_of(c, m);
-        const size_t bytes = (size_t)m[0] * m[1] * m[2] * m[3] * sizeof(pentago_superinfo);
-        e = hipMallocAsync(&scratch[j], bytes, st);
-        if (e != hipSuccess) {
-            scratch[j] = nullptr;
-            rc = hip_fail(e, "hipMallocAsync(child image)");
-            break;
-        }
-        SymJob SJ;
-        rc = make_sym_job(r, rep[j], sym, (pentago_superinfo *)scratch[j], &SJ);
-        if (rc == 0) {
-            e = launch_transform(SJ, T, st);
-            if (e != hipSuccess) rc = hip_fail(e, "transform launch");
-        }
-        child[j] = (const pentago_superinfo *)scratch[j];
+        section_standardize(child_of(s, j), &r, &sym);
+        J.csym[j] = sym;
+        section_shape_of(r, J.rm[j]);
+        for (int k = 0; k < 4; k++) J.rsrc[j][k] = sym_source(sym, k);
     }
-    if (rc == 0) {
-        SweepJob J;
-        rc = make_job(s, child, out, &J, -1, 0);
-        if (rc == 0) rc = run_job(J, T, st);
-    }
-    for (int j = 0; j < 4; j++)
-        if (scratch[j]) (void)hipFreeAsync(scratch[j], st);
-    return rc;
+    return run_job(J, T, (hipStream_t)hip_stream);
 }
 
 }  // extern "C"
