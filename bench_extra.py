@@ -15,8 +15,9 @@
                  and queries/s, against one query per launch.
   serving_resident
                  2^16 queries drawn from the resident sections (random
-                 quadrant turns), answered by lookup: alone, and mixed one to
-                 one with random-play queries under Poisson arrivals.
+                 quadrant turns, then a random one of the 8 board
+                 symmetries), answered by lookup: alone, and mixed one to one
+                 with random-play queries under Poisson arrivals.
   symmetry       the table transform under each of the 7 non-trivial board
                  symmetries of the 36->35 section (6,288,640 entries), and
                  sweeps whose child is held only as its D4 representative
@@ -203,14 +204,18 @@ def serving(P, torch, stream, resident, queries):
 
 def serving_resident(P, torch, stream, resident, queries):
     """Queries drawn from the resident sections (uniform section, uniform
-    entry, every quadrant turned at random) answered by table lookup: alone
+    entry, every quadrant turned at random, the board under a random board
+    symmetry) answered by table lookup: alone
     at full speed, and mixed one to one with the random-play stream under
     Poisson arrivals at 0.7 of the mix's sustained capacity."""
     shapes = [P.pentago_section_shape(c)[0] for c, _ in resident]
     n = 1 << 16
     sec, idx = I.resident_entries(shapes, n, seed=I.SEED_SERVE + 2)
     codes = np.array([P.pentago_section_board(resident[s][0], i) for s, i in zip(sec, idx)], np.uint16)
-    looked = P.boards_to_codes(I.turn_quadrants(I.codes_to_boards(codes), seed=I.SEED_SERVE + 3))
+    # every quadrant turned at random, then every board under a random board
+    # symmetry: the images of the resident sections are answered from them
+    looked = P.boards_to_codes(I.board_symmetries(I.turn_quadrants(I.codes_to_boards(codes), seed=I.SEED_SERVE + 3),
+                                                  seed=I.SEED_SERVE + 5))
     srv = P.Server(memory_budget=4 << 30, max_inflight=1 << 20, max_batch=4096, streams=8)
     for counts, table in resident:
         srv.add_section(counts, table)

@@ -279,9 +279,15 @@ typedef struct {
 int pentago_serve_create(const pentago_serve_config *cfg, pentago_server **out);
 
 /* Register a resident solved section (device table, borrowed until destroy).
- * Queries whose quadrant counts match a resident section are answered by
- * lookup (Section VIII: positions inside the database are read, not solved).
- * EINVAL while queries are in flight: register sections first. */
+ * Queries whose quadrant counts match a resident section, or the image of a
+ * resident section under one of the 8 board symmetries (pentago_section_image;
+ * Section IV stores one section per D4 class), are answered by lookup
+ * (Section VIII: positions inside the database are read, not solved): the
+ * query is mapped to its preimage in the resident section, whose entry is
+ * read, turned back and transformed by the symmetry.  A section registered
+ * itself always takes precedence over an image of another.  EINVAL while
+ * queries are in flight: register sections first; ERANGE beyond 2^24
+ * sections. */
 int pentago_serve_add_section(pentago_server *srv, pentago_section s,
                               const pentago_superinfo *table);
 

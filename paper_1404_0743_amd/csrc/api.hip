@@ -74,7 +74,7 @@ int device_tables(DevTables *out)
         size_t bytes;
         void **dst;
     };
-    void *canon, *qinfo, *lm, *dn, *dr, *sel, *cref, *uref, *smask, *srank, *symmap;
+    void *canon, *qinfo, *lm, *dn, *dr, *sel, *cref, *uref, *smask, *srank, *symmap, *symcode;
     Up ups[] = {{H.canon.data(), H.canon.size() * 2, &canon},
                 {H.qinfo.data(), H.qinfo.size() * sizeof(QInfo), &qinfo},
                 {H.lm.data(), H.lm.size() * sizeof(LineMasks), &lm},
@@ -85,7 +85,8 @@ int device_tables(DevTables *out)
                 {H.u_ref.data(), H.u_ref.size() * 4, &uref},
                 {submask.data(), submask.size() * 2, &smask},
                 {subrank.data(), subrank.size() * 2, &srank},
-                {H.symmap.data(), H.symmap.size() * 2, &symmap}};
+                {H.symmap.data(), H.symmap.size() * 2, &symmap},
+                {H.symcode.data(), H.symcode.size() * 2, &symcode}};
     for (Up &u : ups) {
         e = hipMalloc(&p, u.bytes);
         if (e != hipSuccess) return hip_fail(e, "hipMalloc(tables)");
@@ -104,6 +105,7 @@ int device_tables(DevTables *out)
     T.dag_sub_mask = (const uint16_t *)smask;
     T.dag_sub_rank = (const uint16_t *)srank;
     T.symmap = (const uint16_t *)symmap;
+    T.symcode = (const uint16_t *)symcode;
     g_dev_tables[dev] = T;
     *out = T;
     return 0;

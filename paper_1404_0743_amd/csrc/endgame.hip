@@ -394,7 +394,11 @@ __global__ void __launch_bounds__(256)
 // Resident-section lookup (Section VIII: positions inside the database are
 // read, not solved): each quadrant of the query is turned to its
 // rotation-minimal pattern (k_j turns), the entry is read and shifted back by
-// k_j along every dimension.
+// k_j along every dimension.  When the query's section is the image of the
+// resident one under a board symmetry (Section IV keeps only one section of
+// each D4 class), the query is first mapped back to its preimage in the
+// resident section's frame, and the result is carried over to the query by
+// the symmetry's table transform (no turns: h = 0).
 __global__ void __launch_bounds__(256)
     lookup_kernel(const uint64_t *boards, const int *sec_of, int n, const ResidentSection *secs,
                   uint4 *out, DevTables T)
@@ -402,11 +406,16 @@ __global__ void __launch_bounds__(256)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t b = boards[i];
-    const ResidentSection S = secs[sec_of[i]];
+    const int code = sec_of[i];
+    const ResidentSection S = secs[code & 0xffffff];
+    const int sym = code >> 24;
     int idx[4], k[4];
 #pragma unroll
     for (int j = 0; j < 4; j++) {
-        const uint16_t cc = T.canon[(b >> (16 * j)) & 0xffff];
+        // quadrant j of the query's preimage in the resident section's frame
+        const int q = sym_quadrant(sym, j);
+        const uint32_t c = (uint32_t)(b >> (16 * q)) & 0xffffu;
+        const uint16_t cc = T.canon[sym ? T.symcode[sym * 19683 + c] : c];
         idx[j] = cc & 0xfff;
         k[j] = cc >> 12;
     }
@@ -416,6 +425,12 @@ __global__ void __launch_bounds__(256)
     for (int j = 0; j < 4; j++) {
         W = shift_dim(W, j, k[j]);
         N = shift_dim(N, j, k[j]);
+    }
+    if (sym) {
+        // the query is the symmetry's image of that preimage (Section III:
+        // values are invariant under board symmetries)
+        const int h0[4] = {0, 0, 0, 0};
+        sym_apply_rt2(W, N, sym, h0);
     }
     store_info(out + 4 * (size_t)i, W, N);
 }

@@ -29,6 +29,7 @@ struct DevTables {
     int dag_sub_start[11][12];  // start of size s within layout e
     int dag_sub_max[11];        // largest C(e, s)
     const uint16_t *symmap;     // [8 * kPatterns]: source pattern | turns << 12 per symmetry
+    const uint16_t *symcode;    // [8 * 19683]: preimage of a quadrant code under each symmetry
 };
 
 // The table of the image section sym(s) from the table of s (Section III,
@@ -121,6 +122,8 @@ int dag_lds_bytes(int e);
 int dag_ftab_bytes(int e);
 
 // A solved section kept resident for lookups.
+// A lookup's section code: resident section index | symmetry << 24 (the
+// query's section is the image of the resident one under that symmetry).
 struct ResidentSection {
     const uint4 *table;
     int m[4];

@@ -60,7 +60,9 @@ struct pentago_server {
     pentago_serve_config cfg;
     int device = 0, grid = 0;
     DevTables T;
-    // resident sections
+    // resident sections: section counts -> index into secs | symmetry << 24,
+    // for every registered section and each of its images under the board
+    // symmetries (a registered section itself always maps with symmetry 0)
     std::map<SecKey, int> resident;
     std::vector<ResidentSection> secs;
     ResidentSection *d_secs = nullptr;
@@ -293,11 +295,21 @@ int pentago_serve_add_section(pentago_server *srv, pentago_section s, const pent
     std::lock_guard<std::mutex> lock(srv->mu);
     if (srv->inflight > 0) return fail(PENTAGO_EINVAL, "sections are registered before queries are submitted");
     auto it = srv->resident.find(key_of(s));
-    if (it != srv->resident.end()) {
-        srv->secs[it->second] = r;
+    int index;
+    if (it != srv->resident.end() && (it->second >> 24) == 0) {
+        index = it->second;  // registered before: replace its table
+        srv->secs[index] = r;
     } else {
-        srv->resident[key_of(s)] = (int)srv->secs.size();
+        if (srv->secs.size() >= (1u << 24)) return fail(PENTAGO_ERANGE, "too many resident sections");
+        index = (int)srv->secs.size();
         srv->secs.push_back(r);
+        srv->resident[key_of(s)] = index;
+    }
+    // its images under the board symmetries, unless registered themselves
+    for (int d = 1; d < 8; d++) {
+        const SecKey k = key_of(section_image(s, d));
+        auto jt = srv->resident.find(k);
+        if (jt == srv->resident.end() || (jt->second >> 24) != 0) srv->resident[k] = index | (d << 24);
     }
     if (srv->secs.size() > srv->d_secs_cap) {
         // grow the device copy after the device is idle (lookups in flight

@@ -203,6 +203,13 @@ static void build_symmetry(HostTables &t)
         return code;
     };
     t.symmap.assign(8 * kPatterns, 0);
+    t.symcode.assign(8 * NC, 0);
+    for (int sym = 0; sym < 8; sym++)
+        for (int code = 0; code < NC; code++) {
+            int x = turns(code, 4 - (sym & 3));
+            if (sym & 4) x = mirror1[x];
+            t.symcode[sym * NC + code] = (uint16_t)x;
+        }
     for (int sym = 0; sym < 8; sym++) {
         const int r = sym & 3;
         const bool f = (sym & 4) != 0;

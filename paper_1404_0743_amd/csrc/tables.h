@@ -39,6 +39,9 @@ struct HostTables {
     // the source pattern whose local image is a turn of pattern i, | h << 12,
     // where that local image is pattern i turned h more times (h = 0..3).
     std::vector<uint16_t> symmap;  // [8 * kPatterns]
+    // symcode[sym * 19683 + c]: the quadrant code that the local map of
+    // symmetry sym takes to c (its preimage: mirror^f of c turned -r times).
+    std::vector<uint16_t> symcode;  // [8 * 19683]
 
     // Line structure used by the sweep (five_lut in sweep.hip):
     // sel[(j * 512 + m) * 4 + k] describes the lines through quadrant j that

@@ -220,6 +220,22 @@ def turn_quadrants(boards, seed):
     return b.reshape(-1, 36)
 
 
+def board_symmetries(boards, seed):
+    """Every board under an independent uniform one of the 8 board
+    symmetries (the mirror numpy.fliplr or not, then 0..3 numpy.rot90
+    quarter turns of the 6x6 array)."""
+    rng = np.random.default_rng(seed)
+    b = np.array(boards, dtype=np.uint8).reshape(-1, 6, 6)
+    k = rng.integers(0, 8, size=len(b))
+    out = b.copy()
+    for sym in range(1, 8):
+        sel = k == sym
+        if sel.any():
+            x = b[sel][:, :, ::-1] if sym & 4 else b[sel]
+            out[sel] = np.rot90(x, sym & 3, axes=(1, 2))
+    return out.reshape(-1, 36)
+
+
 def resident_entries(section_sizes, n, seed):
     """n (section number, entry number) pairs: a uniform section, then a
     uniform entry of it.  section_sizes: the shape (4 extents) of each."""

@@ -130,3 +130,31 @@ def test_replay_open_loop(P, resident):
     srv.close()
     assert st["queries"] == len(codes)
     assert np.array_equal(res, O.minimax_tables(boards))
+
+
+def test_lookups_through_board_symmetries(P, resident):
+    """Boards of every image of the resident section under the 8 board
+    symmetries (quadrants also turned at random) are answered by lookup in
+    the one resident table, and equal the oracle's minimax tables."""
+    log("serve symmetric lookups")
+    rng = np.random.default_rng(9)
+    shape = O.section_shape(RESIDENT)
+    boards, syms = [], []
+    for k in range(160):
+        sym = k % 8
+        b = O.section_board(RESIDENT, [rng.integers(0, m) for m in shape])
+        b = O.apply(b, int(rng.integers(0, 256)))
+        img = np.zeros(36, np.uint8)
+        img[O.sym_cells(sym)] = b
+        boards.append(img)
+        syms.append(sym)
+    boards = np.array(boards)
+    assert len({O.sym_counts(RESIDENT, s) for s in range(8)}) == 8
+    codes = P.boards_to_codes(boards)
+    srv = P.Server(memory_budget=1 << 30, max_inflight=4096, max_batch=64, streams=2)
+    srv.add_section(RESIDENT, resident)
+    got = run_all(P, srv, codes)
+    st = srv.stats()
+    srv.close()
+    assert st["lookups"] == len(boards) and st["searches"] == 0
+    assert np.array_equal(got, O.minimax_tables(boards))
