@@ -112,6 +112,13 @@ int pentago_child_section(pentago_section s, int j, pentago_section *child);
  * quadrant q move to quadrant pi(q).  EINVAL for invalid counts or sym. */
 int pentago_section_image(pentago_section s, int sym, pentago_section *image);
 
+/* The sections of the slice with `stones` stones whose counts are least
+ * among their images under the board symmetries (Section IV: the sections a
+ * slice sweep computes), in lexicographic order of the count tuples.  Writes
+ * at most cap of them to out; *count = how many there are (call with cap 0
+ * to size out).  Host only.  EINVAL for stones outside 0..36. */
+int pentago_slice_sections(int stones, pentago_section *out, size_t cap, size_t *count);
+
 /* The representative of s under the board symmetries (Section IV: only
  * sections whose count tuple ((b0,w0),(b1,w1),(b2,w2),(b3,w3)) is least in
  * lexicographic order among its images are computed): *rep is that least
@@ -208,6 +215,13 @@ typedef struct {
  * write to any table another job of the same call reads.  n <= 65536. */
 int pentago_solve_sections(const pentago_section_job *jobs, size_t n, void *hip_stream);
 
+/* The same with every job's children held as their representatives under
+ * the board symmetries (child[j] as rep[j] of pentago_solve_section_d4): the
+ * layer step of a whole-slice sweep that stores only D4-minimal sections
+ * (Section IV).  Results are bit-identical to pentago_solve_section_d4 on
+ * each job. */
+int pentago_solve_sections_d4(const pentago_section_job *jobs, size_t n, void *hip_stream);
+
 /* A sweep plan: the job table of one layer (as for pentago_solve_sections)
  * uploaded once, with the prepared-child buffers it needs, so that the layer
  * can be launched repeatedly, directly or from a captured hipGraph.  The
@@ -215,6 +229,8 @@ int pentago_solve_sections(const pentago_section_job *jobs, size_t n, void *hip_
  * pentago_plan_create synchronises the device while uploading. */
 typedef struct pentago_sweep_plan pentago_sweep_plan;
 int pentago_plan_create(const pentago_section_job *jobs, size_t n, pentago_sweep_plan **plan);
+/* A plan whose jobs' children are representatives (as pentago_solve_sections_d4). */
+int pentago_plan_create_d4(const pentago_section_job *jobs, size_t n, pentago_sweep_plan **plan);
 /* Enqueue the layer on hip_stream: one batched prep launch (children along
  * dimensions that are not staged) and one persistent sweep launch. */
 int pentago_plan_launch(pentago_sweep_plan *plan, void *hip_stream);

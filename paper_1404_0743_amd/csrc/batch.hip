@@ -25,6 +25,7 @@ struct pentago_sweep_plan {
     long long *d_chunk_start = nullptr;
     unsigned long long *d_counter = nullptr;
     bool async_alloc = false;
+    bool sym = false;  // children held as their representatives
     hipStream_t capture = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -39,7 +40,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // dimensions that are not staged, and the device block holding all of it.
 // With `stream` the device block is allocated stream-ordered on it.
 static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t stream, bool async,
-                      pentago_sweep_plan **out)
+                      bool reps, pentago_sweep_plan **out)
 {
     if (!jobs || n == 0) return fail(PENTAGO_EINVAL, "no jobs");
     if (n > 65536) return fail(PENTAGO_ERANGE, "more than 65536 jobs");
@@ -50,6 +51,7 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
             return fail(PENTAGO_EINVAL, "jobs of one call must share the stone count");
         int rc = make_job(jobs[i].section, jobs[i].child, jobs[i].out, &J[i], -1, 0);
         if (rc) return rc;
+        if (reps) set_child_syms(jobs[i].section, jobs[i].child, &J[i]);
     }
     // largest sections first: their tiles start early and small ones fill the tail
     std::vector<size_t> order(n);
@@ -93,9 +95,10 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
     P->total_chunks = chunks;
     P->lds_bytes = lds;
     P->async_alloc = async;
+    P->sym = reps;
     int cus = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device);
-    P->grid = std::max(1, cus) * sweep_batch_blocks_per_cu(lds);
+    P->grid = std::max(1, cus) * sweep_batch_blocks_per_cu(lds, reps);
 
     const size_t o_jobs = 0;
     const size_t o_tiles = align256(o_jobs + n * sizeof(SweepJob));
@@ -141,7 +144,7 @@ static int plan_enqueue(pentago_sweep_plan *P, hipStream_t st)
                                      P->total_chunks, P->T, st);
     if (e == hipSuccess)
         e = launch_sweep_batch(P->d_jobs, P->d_tile_start, P->njobs, P->total_tiles, P->lds_bytes,
-                               P->d_counter, P->grid, P->T, st);
+                               P->d_counter, P->grid, P->sym, P->T, st);
     if (e != hipSuccess) return hip_fail(e, "batched sweep launch");
     return 0;
 }
@@ -153,7 +156,13 @@ extern "C" {
 int pentago_plan_create(const pentago_section_job *jobs, size_t n, pentago_sweep_plan **plan)
 {
     if (!plan) return fail(PENTAGO_EINVAL, "plan is NULL");
-    return plan_build(jobs, n, nullptr, false, plan);
+    return plan_build(jobs, n, nullptr, false, false, plan);
+}
+
+int pentago_plan_create_d4(const pentago_section_job *jobs, size_t n, pentago_sweep_plan **plan)
+{
+    if (!plan) return fail(PENTAGO_EINVAL, "plan is NULL");
+    return plan_build(jobs, n, nullptr, false, true, plan);
 }
 
 int pentago_plan_launch(pentago_sweep_plan *plan, void *hip_stream)
@@ -203,16 +212,26 @@ int pentago_plan_destroy(pentago_sweep_plan *plan)
     return 0;
 }
 
-int pentago_solve_sections(const pentago_section_job *jobs, size_t n, void *hip_stream)
+static int solve_sections(const pentago_section_job *jobs, size_t n, void *hip_stream, bool reps)
 {
     const hipStream_t st = (hipStream_t)hip_stream;
     pentago_sweep_plan *P = nullptr;
-    int rc = plan_build(jobs, n, st, true, &P);
+    int rc = plan_build(jobs, n, st, true, reps, &P);
     if (rc) return rc;
     rc = plan_enqueue(P, st);
     (void)hipFreeAsync(P->dev, st);
     delete P;
     return rc;
+}
+
+int pentago_solve_sections(const pentago_section_job *jobs, size_t n, void *hip_stream)
+{
+    return solve_sections(jobs, n, hip_stream, false);
+}
+
+int pentago_solve_sections_d4(const pentago_section_job *jobs, size_t n, void *hip_stream)
+{
+    return solve_sections(jobs, n, hip_stream, true);
 }
 
 }  // extern "C"

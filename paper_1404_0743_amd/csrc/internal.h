@@ -34,6 +34,7 @@ TileShape tuned_tile_shape(const SweepJob &J);
 void remember_tile_shape(const SweepJob &J, TileShape t);
 pentago_section section_image(const pentago_section &s, int sym);
 void section_standardize(const pentago_section &s, pentago_section *rep, int *sym);
+void set_child_syms(const pentago_section &s, const pentago_superinfo *const rep[4], SweepJob *J);
 int make_sym_job(const pentago_section &s, const pentago_superinfo *table, int sym,
                  pentago_superinfo *out, SymJob *J);
 int eval_grid(int *grid);

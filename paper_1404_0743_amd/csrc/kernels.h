@@ -88,10 +88,11 @@ hipError_t launch_prep(const SweepJob &job, int j, const DevTables &T, hipStream
 hipError_t launch_prep_batch(const SweepJob *dev_jobs, const int *dev_unit,
                              const long long *dev_chunk_start, int nunits, long long total_chunks,
                              const DevTables &T, hipStream_t s);
-int sweep_batch_blocks_per_cu(int lds_bytes);
+// sym: jobs whose children may be held as their representatives (csym).
+int sweep_batch_blocks_per_cu(int lds_bytes, bool sym);
 hipError_t launch_sweep_batch(const SweepJob *dev_jobs, const long long *dev_tile_start, int njobs,
                               long long total_tiles, int lds_bytes, unsigned long long *dev_counter,
-                              int grid, const DevTables &T, hipStream_t s);
+                              int grid, bool sym, const DevTables &T, hipStream_t s);
 
 // Endgame (Section VIII serial solver, one DAG per root).
 struct EvalScratch {

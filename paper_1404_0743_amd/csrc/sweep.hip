@@ -618,9 +618,12 @@ __global__ void __launch_bounds__(NT, NT == 512 ? (SYMC ? 5 : 6) : 1) sweep_kern
 
 // Many sections in one persistent launch: workgroups take tiles from a
 // device counter; tile_start[j] is the first global tile of job j.
-__global__ void __launch_bounds__(256)
-    sweep_batch_kernel(const SweepJob *jobs, const long long *tile_start, int njobs,
-                       long long total, unsigned long long *counter, DevTables T)
+// Persistent loop of the batched sweep: workgroups take tiles from the
+// device counter until the layer is done.  SYMS: some staged children are
+// held as their representatives (sweep_tile<D, true> for those jobs).
+template <bool SYMS>
+__device__ void sweep_batch_loop(const SweepJob *jobs, const long long *tile_start, int njobs,
+                                 long long total, unsigned long long *counter, const DevTables &T)
 {
     extern __shared__ uint4 lds[];
     __shared__ long long s_tile;
@@ -638,15 +641,41 @@ __global__ void __launch_bounds__(256)
         }
         const SweepJob &J = jobs[lo];
         const long long local = t - tile_start[lo];
-        switch (J.d) {
-        case 0: sweep_tile<0>(J, T, local, (void *)lds); break;
-        case 1: sweep_tile<1>(J, T, local, (void *)lds); break;
-        case 2: sweep_tile<2>(J, T, local, (void *)lds); break;
-        default: sweep_tile<3>(J, T, local, (void *)lds); break;
+        const bool symc = SYMS && J.csym[J.d] != 0 && ((J.emask >> J.d) & 1) && !((J.odmask >> J.d) & 1);
+        if (symc) {
+            switch (J.d) {
+            case 0: sweep_tile<0, SYMS>(J, T, local, (void *)lds); break;
+            case 1: sweep_tile<1, SYMS>(J, T, local, (void *)lds); break;
+            case 2: sweep_tile<2, SYMS>(J, T, local, (void *)lds); break;
+            default: sweep_tile<3, SYMS>(J, T, local, (void *)lds); break;
+            }
+        } else {
+            switch (J.d) {
+            case 0: sweep_tile<0>(J, T, local, (void *)lds); break;
+            case 1: sweep_tile<1>(J, T, local, (void *)lds); break;
+            case 2: sweep_tile<2>(J, T, local, (void *)lds); break;
+            default: sweep_tile<3>(J, T, local, (void *)lds); break;
+            }
         }
         __syncthreads();
     }
 }
+
+__global__ void __launch_bounds__(256)
+    sweep_batch_kernel(const SweepJob *jobs, const long long *tile_start, int njobs,
+                       long long total, unsigned long long *counter, DevTables T)
+{
+    sweep_batch_loop<false>(jobs, tile_start, njobs, total, counter, T);
+}
+
+// The same over jobs whose children may be held as their representatives.
+__global__ void __launch_bounds__(256)
+    sweep_batch_sym_kernel(const SweepJob *jobs, const long long *tile_start, int njobs,
+                           long long total, unsigned long long *counter, DevTables T)
+{
+    sweep_batch_loop<true>(jobs, tile_start, njobs, total, counter, T);
+}
+
 
 
 hipError_t launch_prep(const SweepJob &job, int j, const DevTables &T, hipStream_t s)
@@ -722,21 +751,26 @@ hipError_t launch_prep_batch(const SweepJob *dev_jobs, const int *dev_unit,
     return hipGetLastError();
 }
 
-int sweep_batch_blocks_per_cu(int lds_bytes)
+int sweep_batch_blocks_per_cu(int lds_bytes, bool sym)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_batch_kernel, 256, lds_bytes) != hipSuccess)
-        return 1;
+    const hipError_t e = sym ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_batch_sym_kernel, 256, lds_bytes)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_batch_kernel, 256, lds_bytes);
+    if (e != hipSuccess) return 1;
     return std::max(1, n);
 }
 
 hipError_t launch_sweep_batch(const SweepJob *dev_jobs, const long long *dev_tile_start, int njobs,
                               long long total_tiles, int lds_bytes, unsigned long long *dev_counter,
-                              int grid, const DevTables &T, hipStream_t s)
+                              int grid, bool sym, const DevTables &T, hipStream_t s)
 {
     hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, dev_counter, 1);
-    hipLaunchKernelGGL(sweep_batch_kernel, dim3(grid), dim3(256), lds_bytes, s, dev_jobs,
-                       dev_tile_start, njobs, total_tiles, dev_counter, T);
+    if (sym)
+        hipLaunchKernelGGL(sweep_batch_sym_kernel, dim3(grid), dim3(256), lds_bytes, s, dev_jobs,
+                           dev_tile_start, njobs, total_tiles, dev_counter, T);
+    else
+        hipLaunchKernelGGL(sweep_batch_kernel, dim3(grid), dim3(256), lds_bytes, s, dev_jobs,
+                           dev_tile_start, njobs, total_tiles, dev_counter, T);
     return hipGetLastError();
 }
 

@@ -158,6 +158,24 @@ void section_standardize(const pentago_section &s, pentago_section *rep, int *sy
     *sym = sym_inverse(bestd);
 }
 
+// Mark the children of a sweep job as held by their representatives: for
+// each quadrant with a child table, the symmetry taking the representative
+// to the child, the representative's shape and which of its dimensions
+// feeds each child dimension.
+void set_child_syms(const pentago_section &s, const pentago_superinfo *const rep[4], SweepJob *J)
+{
+    for (int j = 0; j < 4; j++) {
+        J->csym[j] = 0;
+        if (!rep[j] || s.black[j] + s.white[j] == 9) continue;
+        pentago_section r;
+        int sym = 0;
+        section_standardize(child_of(s, j), &r, &sym);
+        J->csym[j] = sym;
+        section_shape_of(r, J->rm[j]);
+        for (int k = 0; k < 4; k++) J->rsrc[j][k] = sym_source(sym, k);
+    }
+}
+
 int make_sym_job(const pentago_section &s, const pentago_superinfo *table, int sym,
                  pentago_superinfo *out, SymJob *J)
 {
@@ -230,16 +248,38 @@ int pentago_solve_section_d4(pentago_section s, const pentago_superinfo *const r
     SweepJob J;
     rc = make_job(s, rep, out, &J, -1, 0);
     if (rc) return rc;
-    for (int j = 0; j < 4; j++) {
-        if (!rep[j] || s.black[j] + s.white[j] == 9) continue;
-        pentago_section r;
-        int sym = 0;
-        section_standardize(child_of(s, j), &r, &sym);
-        J.csym[j] = sym;
-        section_shape_of(r, J.rm[j]);
-        for (int k = 0; k < 4; k++) J.rsrc[j][k] = sym_source(sym, k);
-    }
+    set_child_syms(s, rep, &J);
     return run_job(J, T, (hipStream_t)hip_stream);
+}
+
+int pentago_slice_sections(int stones, pentago_section *out, size_t cap, size_t *count)
+{
+    if (stones < 0 || stones > 36 || !count || (cap && !out)) return fail(PENTAGO_EINVAL, "invalid arguments");
+    const int tb = (stones + 1) / 2, tw = stones / 2;
+    size_t n = 0;
+    pentago_section s;
+    for (int b0 = 0; b0 <= 9; b0++)
+        for (int w0 = 0; b0 + w0 <= 9; w0++)
+            for (int b1 = 0; b1 <= 9; b1++)
+                for (int w1 = 0; b1 + w1 <= 9; w1++)
+                    for (int b2 = 0; b2 <= 9; b2++)
+                        for (int w2 = 0; b2 + w2 <= 9; w2++) {
+                            const int b3 = tb - b0 - b1 - b2, w3 = tw - w0 - w1 - w2;
+                            if (b3 < 0 || w3 < 0 || b3 + w3 > 9) continue;
+                            const int bs[4] = {b0, b1, b2, b3}, ws[4] = {w0, w1, w2, w3};
+                            for (int q = 0; q < 4; q++) {
+                                s.black[q] = (uint8_t)bs[q];
+                                s.white[q] = (uint8_t)ws[q];
+                            }
+                            pentago_section r;
+                            int sym;
+                            section_standardize(s, &r, &sym);
+                            if (sym != 0 || memcmp(&r, &s, sizeof(s)) != 0) continue;
+                            if (n < cap) out[n] = s;
+                            n++;
+                        }
+    *count = n;
+    return 0;
 }
 
 }  // extern "C"

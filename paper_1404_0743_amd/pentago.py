@@ -71,6 +71,9 @@ _SIGS = {
     "pentago_section_transform": ([Section, _P, ctypes.c_int, _P, _P], ctypes.c_int),
     "pentago_solve_section_d4": ([Section, _P, _P, _P], ctypes.c_int),
     "pentago_solve_sections": ([_P, ctypes.c_size_t, _P], ctypes.c_int),
+    "pentago_solve_sections_d4": ([_P, ctypes.c_size_t, _P], ctypes.c_int),
+    "pentago_plan_create_d4": ([_P, ctypes.c_size_t, _P], ctypes.c_int),
+    "pentago_slice_sections": ([ctypes.c_int, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "pentago_autotune_section": ([Section, _P, _P, _P, _P, _P], ctypes.c_int),
     "pentago_solve_section_shape": ([Section, _P, _P, _P, _P], ctypes.c_int),
     "pentago_plan_create": ([_P, ctypes.c_size_t, _P], ctypes.c_int),
@@ -291,14 +294,32 @@ def pentago_solve_sections(jobs, stream=None):
     _check(lib().pentago_solve_sections(arr, len(jobs), _stream(stream)), "pentago_solve_sections")
 
 
-class SweepPlan:
-    """pentago_plan_*: one layer's job table kept on the device."""
+def pentago_solve_sections_d4(jobs, stream=None):
+    """jobs: list of (counts, tables of the children's representatives (4
+    tensors or None), out tensor)."""
+    arr = _job_array(jobs)
+    _check(lib().pentago_solve_sections_d4(arr, len(jobs), _stream(stream)), "pentago_solve_sections_d4")
 
-    def __init__(self, jobs):
+
+def pentago_slice_sections(stones):
+    """The D4-minimal sections of a slice, in lexicographic order of counts."""
+    n = ctypes.c_size_t()
+    _check(lib().pentago_slice_sections(int(stones), None, 0, ctypes.byref(n)), "pentago_slice_sections")
+    arr = (Section * max(1, n.value))()
+    _check(lib().pentago_slice_sections(int(stones), arr, n.value, ctypes.byref(n)), "pentago_slice_sections")
+    return [_counts_of(arr[k]) for k in range(n.value)]
+
+
+class SweepPlan:
+    """pentago_plan_*: one layer's job table kept on the device (reps=True:
+    the children are the representatives' tables, pentago_plan_create_d4)."""
+
+    def __init__(self, jobs, reps=False):
         self._keep = jobs
         h = ctypes.c_void_p()
-        _check(lib().pentago_plan_create(_job_array(jobs), len(jobs), ctypes.byref(h)),
-               "pentago_plan_create")
+        f = lib().pentago_plan_create_d4 if reps else lib().pentago_plan_create
+        _check(f(_job_array(jobs), len(jobs), ctypes.byref(h)),
+               "pentago_plan_create" + ("_d4" if reps else ""))
         self.h = h
 
     def launch(self, stream=None, graph=False):

@@ -100,3 +100,15 @@ def test_image_and_standardize_match_layout_arithmetic():
         assert P.pentago_section_image(rep, sym) == s
         if C.is_d4_minimal(s):
             assert (rep, sym) == (s, 0)
+
+
+def test_slice_sections_match_layout_arithmetic():
+    most = 0
+    for n in range(37):
+        got = P.pentago_slice_sections(n)
+        assert got == list(C.slice_sections(n, minimal_only=True)), n
+        most = max(most, len(got))
+    assert most == 8239   # at most 8239 sections per slice (Section IV)
+    from paper_1404_0743_amd import slices
+    assert slices.slice_positions(35, minimal_only=False) == sum(
+        O.section_entries(s) and C.boards(s) for s in C.slice_sections(35, minimal_only=False))
