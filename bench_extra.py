@@ -18,6 +18,9 @@
                  quadrant turns, then a random one of the 8 board
                  symmetries), answered by lookup: alone, and mixed one to one
                  with random-play queries under Poisson arrivals.
+  slices         whole slices 35 and 34 (330 and 750 D4-minimal sections, 7.7
+                 and 63 GB) over representatives: one batched launch, a
+                 hipGraph replay, and one launch per section.
   symmetry       the table transform under each of the 7 non-trivial board
                  symmetries of the 36->35 section (6,288,640 entries), and
                  sweeps whose child is held only as its D4 representative
@@ -297,7 +300,55 @@ def symmetry(P, torch, stream, resident):
     return res
 
 
-NAMES = ("endgame_4096", "endgame_2p20", "layers", "serving", "serving_resident", "symmetry")
+NAMES = ("endgame_4096", "endgame_2p20", "layers", "serving", "serving_resident", "symmetry", "slices")
+
+
+def slices(P, torch, stream):
+    """Whole slices 35 and 34 over D4 representatives: every D4-minimal
+    section of the slice, children read from the representatives of the
+    slice above (slice 35: the 36-stone boards on demand).  One batched
+    launch, the same replayed from a hipGraph, and one launch per section;
+    all three must leave the same tables."""
+    from paper_1404_0743_amd import slices as S
+    res = {}
+    above = None
+    for stones in (35, 34):
+        jobs, tables = S.slice_jobs(stones, above)
+        entries = sum(t.shape[0] for t in tables.values())
+        reads = 0
+        for counts, children, _ in jobs:
+            reads += sum(c.shape[0] for c in children if c is not None)
+        alg = 64 * entries + 64 * reads
+        t_batched, _ = _time(torch, stream, lambda: P.pentago_solve_sections_d4(jobs, stream), 5)
+        keep = {k: v.clone() for k, v in sorted(tables.items(), key=lambda kv: -kv[1].shape[0])[:8]}
+        w = torch.randint(-(1 << 62), 1 << 62, (8,), dtype=torch.int64, device="cuda")
+        check = lambda: [int((t * w).sum()) for t in tables.values()]
+        sums = check()
+        plan = P.SweepPlan(jobs, reps=True)
+        t_graph, _ = _time(torch, stream, lambda: plan.launch(stream, graph=True), 5)
+        same = check() == sums and all(torch.equal(tables[k], v) for k, v in keep.items())
+        plan.close()
+
+        def per_section():
+            for counts, children, out in jobs:
+                P.pentago_solve_section_d4(counts, children, out, stream)
+        t_plain, _ = _time(torch, stream, per_section, 3)
+        same = same and check() == sums and all(torch.equal(tables[k], v) for k, v in keep.items())
+        pos = S.slice_positions(stones)
+        cover = S.slice_positions(stones, minimal_only=False)
+        res["slice%d" % stones] = {
+            "sections": len(jobs), "entries": entries, "bytes_written": 64 * entries,
+            "positions": pos, "positions_all_images": cover,
+            "batched_ms": t_batched, "graph_ms": t_graph, "per_section_ms": t_plain,
+            "graph_positions_per_s": pos / (t_graph * 1e-3),
+            "graph_positions_all_images_per_s": cover / (t_graph * 1e-3),
+            "graph_algorithmic_GB_s": alg / (t_graph * 1e-3) / 1e9,
+            "graph_over_per_section": t_plain / t_graph, "same_bytes": bool(same)}
+        del keep
+        above = tables
+    del above
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_all(P, torch, stream, boards_2p20=None, serve_queries=None, resident=None, only=None):
@@ -307,7 +358,8 @@ def run_all(P, torch, stream, boards_2p20=None, serve_queries=None, resident=Non
                      ("layers", lambda: layers(P, torch, stream, resident)),
                      ("serving", lambda: serving(P, torch, stream, resident, serve_queries)),
                      ("serving_resident", lambda: serving_resident(P, torch, stream, resident, serve_queries)),
-                     ("symmetry", lambda: symmetry(P, torch, stream, resident))):
+                     ("symmetry", lambda: symmetry(P, torch, stream, resident)),
+                     ("slices", lambda: slices(P, torch, stream))):
         if only is not None and name not in only:
             continue
         if name == "endgame_2p20" and boards_2p20 is None:

@@ -36,6 +36,9 @@ namespace pg {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// LDS bound of one batched tile (bytes).
+constexpr int kBatchLds = 40960;
+
 // Build a plan: job table in decreasing order of work, prep units for the
 // dimensions that are not staged, and the device block holding all of it.
 // With `stream` the device block is allocated stream-ordered on it.
@@ -51,6 +54,15 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
             return fail(PENTAGO_EINVAL, "jobs of one call must share the stone count");
         int rc = make_job(jobs[i].section, jobs[i].child, jobs[i].out, &J[i], -1, 0);
         if (rc) return rc;
+        // the persistent grid's occupancy follows the largest tile's LDS: keep
+        // every tile within kBatchLds by taking fewer lines per tile
+        if (J[i].lds_bytes > kBatchLds && J[i].G > 1) {
+            int G = J[i].G;
+            const int cmd = (J[i].emask >> J[i].d) & 1 ? J[i].cm[J[i].d] : 0;
+            while (G > 1 && sweep_lds_bytes(G, J[i].m[J[i].d], cmd) > kBatchLds) G--;
+            rc = make_job(jobs[i].section, jobs[i].child, jobs[i].out, &J[i], J[i].d, G);
+            if (rc) return rc;
+        }
         if (reps) set_child_syms(jobs[i].section, jobs[i].child, &J[i]);
     }
     // largest sections first: their tiles start early and small ones fill the tail

@@ -330,8 +330,10 @@ int sweep_lds_bytes(int G, int mD, int cmD)
 }
 
 // SYMC: the staged child is held as its representative (J.csym[D] != 0).
+// Always inlined: the persistent kernels hold several instantiations, and a
+// call would spill the caller's registers to scratch.
 template <int D, bool SYMC = false>
-__device__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile, void *lds_base)
+__device__ __forceinline__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile, void *lds_base)
 {
     // tile = ((i_O1 * m_O2) + i_O2) * ngroups + group of G lines along E
     constexpr int E = D == 3 ? 2 : 3;
@@ -622,7 +624,7 @@ __global__ void __launch_bounds__(NT, NT == 512 ? (SYMC ? 5 : 6) : 1) sweep_kern
 // device counter until the layer is done.  SYMS: some staged children are
 // held as their representatives (sweep_tile<D, true> for those jobs).
 template <bool SYMS>
-__device__ void sweep_batch_loop(const SweepJob *jobs, const long long *tile_start, int njobs,
+__device__ __forceinline__ void sweep_batch_loop(const SweepJob *jobs, const long long *tile_start, int njobs,
                                  long long total, unsigned long long *counter, const DevTables &T)
 {
     extern __shared__ uint4 lds[];
