@@ -267,6 +267,20 @@ int pentago_eval_batch(const pentago_board *boards, size_t n, pentago_superinfo 
 int pentago_eval_batch_grouped(const pentago_board *boards, size_t n, pentago_superinfo *out,
                                int32_t *status, void *hip_stream);
 
+/* Exact superinfo of one deep position, solved to the full board over all
+ * 256 quadrant rotations (Section VIII: positions outside the database are
+ * solved from scratch; the paper's serial solver evaluates an 18-stone
+ * position in 16 s on one CPU thread).  The root's DAG (every way to fill its
+ * e empty cells in alternating colours; 86,574,831 nodes for e = 18) is
+ * solved layer by layer across the whole GPU, two layers at a time in HBM.
+ *   out   device, 64 B.
+ * Device scratch (two layers of 64 B records: 2.2 GB for e = 18, 6 GB for
+ * e = 20) is allocated stream-ordered on hip_stream and released after the
+ * call's work.  Stream-ordered and asynchronous.  EINVAL for invalid codes or
+ * stone counts; ERANGE for more than 20 empty cells; EDEVICE when the scratch
+ * allocation fails. */
+int pentago_eval_deep(pentago_board board, pentago_superinfo *out, void *hip_stream);
+
 /* ---------------------------------------------------------------- serving */
 
 typedef struct pentago_server pentago_server;

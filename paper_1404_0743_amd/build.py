@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpentago.so")
 SOURCES = ["tables.cpp", "sweep.hip", "endgame.hip", "api.hip", "eval.hip", "debug.hip", "tune.hip", "batch.hip",
-           "serve.hip", "symmetry.hip"]
+           "serve.hip", "symmetry.hip",
+           "deep.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-pthread"]

@@ -82,6 +82,7 @@ _SIGS = {
     "pentago_plan_info": ([_P, _P, _P, _P], ctypes.c_int),
     "pentago_plan_destroy": ([_P], ctypes.c_int),
     "pentago_eval_batch": ([_P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
+    "pentago_eval_deep": ([Board, _P, _P], ctypes.c_int),
     "pentago_eval_batch_grouped": ([_P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
     "pentago_serve_create": ([_P, _P], ctypes.c_int),
     "pentago_serve_add_section": ([_P, Section, _P], ctypes.c_int),
@@ -345,6 +346,12 @@ class SweepPlan:
 
 
 # ---------------------------------------------------------------- endgame
+
+def pentago_eval_deep(codes, out, stream=None):
+    """One board (4 quadrant codes) solved from scratch; out: device tensor
+    of 8 int64 (64 B)."""
+    _check(lib().pentago_eval_deep(board(codes), _dev_ptr(out), _stream(stream)), "pentago_eval_deep")
+
 
 def pentago_eval_batch(boards, out, status=None, stream=None, grouped=False):
     """boards: device tensor (n, 4) int16/uint16 codes (or n x 8 bytes); out:

@@ -1,0 +1,160 @@
+"""GPU tests of the deep endgame solver (pentago_eval_deep; Section VIII:
+positions outside the database solved from scratch, one root's DAG spread
+over the GPU layer by layer).
+
+Parity: against the oracle's minimax search (O2) for roots with up to four
+empty cells, and against the batched endgame solver (itself pinned to O2) for
+1..10 empty cells.  Beyond that, properties that hold at any size: a root's
+table follows from the tables of its placements by the Section II recurrence
+(checked bit by bit at 12 empty cells, every placement solved separately),
+and tables are carried into each other by the board symmetries (14 empty
+cells).  Full boards, boards showing fives, and argument errors."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1404_0743_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1404_0743_amd import pentago
+    pentago.lib()
+    return pentago
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def deep(P, board):
+    out = torch.zeros(8, dtype=torch.int64, device="cuda")
+    P.pentago_eval_deep(P.boards_to_codes(np.asarray(board).reshape(1, 36))[0], out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint64)
+
+
+def batch(P, boards):
+    codes = P.boards_to_codes(np.asarray(boards).reshape(-1, 36))
+    dev = torch.from_numpy(codes.view(np.int16).copy()).cuda()
+    out = torch.empty((len(codes), 8), dtype=torch.int64, device="cuda")
+    P.pentago_eval_batch(dev, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint64)
+
+
+def test_small_roots_match_minimax(P):
+    boards = I.random_play_boards(24, 32, 35, seed=71)
+    boards = np.concatenate([boards, I.random_placement_boards(8, 18, 18, seed=72)])
+    want = O.minimax_tables(boards)
+    for k, b in enumerate(boards):
+        log("deep vs minimax", k)
+        assert np.array_equal(deep(P, b), want[k]), k
+
+
+def test_roots_match_batched_solver_up_to_10_empty(P):
+    boards = I.random_play_boards(60, 26, 35, seed=73)
+    want = batch(P, boards)
+    for k, b in enumerate(boards):
+        log("deep vs batch", k, "empties", int((b == 0).sum()))
+        assert np.array_equal(deep(P, b), want[k]), k
+
+
+def values(t):
+    """8 uint64 -> int8[256] values (win + notlose - 1)."""
+    return O.table_values(np.asarray(t, dtype=np.uint64).reshape(1, 8))[0]
+
+
+def test_root_follows_from_its_placements_at_12_empty(P):
+    """v(g.s) = terminal value if g.s shows a five, else the max over empty
+    cells p of +1 when placing at p makes the mover's five, else the max over
+    the 8 single-quadrant turns r of -v_t(g + r), t = s with the stone on p
+    (Section II; turns commute with placements, Section III)."""
+    root = I.random_play_boards(1, 24, 24, seed=74)[0]
+    mover = O.mover(root)
+    other = 3 - mover
+    got = values(deep(P, root))
+    cells = np.nonzero(root == 0)[0]
+    assert len(cells) == 12
+    child = {}
+    for p in cells:
+        t = root.copy()
+        t[p] = mover
+        log("placement", int(p))
+        child[int(p)] = (t, values(deep(P, t)))
+    want = np.zeros(256, np.int8)
+    for g in range(256):
+        gs = O.apply(root, g)
+        fx, fy = O.five(gs, mover), O.five(gs, other)
+        if fx or fy:
+            want[g] = int(fx) - int(fy)
+            continue
+        best = -1
+        for p, (t, vt) in child.items():
+            if O.five(O.apply(t, g), mover):
+                best = 1
+                break
+            for j in range(4):
+                for d in (1, 3):
+                    gr = (g & ~(3 << (2 * j))) | ((((g >> (2 * j)) + d) & 3) << (2 * j))
+                    best = max(best, -int(vt[gr]))
+        want[g] = best
+    assert np.array_equal(got, want)
+
+
+def test_symmetric_roots_at_14_empty(P):
+    root = I.random_play_boards(1, 22, 22, seed=75)[0]
+    base = deep(P, root)
+    for sym in (1, 4, 6):
+        img = np.zeros(36, np.uint8)
+        img[O.sym_cells(sym)] = root
+        log("symmetry", sym)
+        got = deep(P, img)
+        want = np.concatenate([P.pentago_debug_sym(base[:4], sym, [0, 0, 0, 0]),
+                               P.pentago_debug_sym(base[4:], sym, [0, 0, 0, 0])])
+        assert np.array_equal(got, want), sym
+
+
+def test_full_boards_and_fives(P):
+    full = I.random_placement_boards(4, 18, 18, seed=76)
+    # boards with two empty cells that already show a five (of either side)
+    rng = np.random.default_rng(77)
+    fives = []
+    while len(fives) < 6:
+        b = np.zeros(36, np.uint8)
+        perm = rng.permutation(36)
+        b[perm[:17]] = 1
+        b[perm[17:34]] = 2
+        if I.has_five(b, 1)[0] or I.has_five(b, 2)[0]:
+            fives.append(b)
+    boards = np.concatenate([full, np.array(fives)])
+    want = O.minimax_tables(boards)
+    for k, b in enumerate(boards):
+        assert np.array_equal(deep(P, b), want[k]), k
+
+
+def test_errors(P):
+    out = torch.zeros(8, dtype=torch.int64, device="cuda")
+    with pytest.raises(P.PentagoError) as e:
+        P.pentago_eval_deep((19683, 0, 0, 0), out)
+    assert e.value.code == P.EINVAL
+    b = np.zeros(36, np.uint8)
+    b[[0, 1]] = 1                          # two black stones, no white: invalid counts
+    with pytest.raises(P.PentagoError) as e:
+        P.pentago_eval_deep(P.boards_to_codes(b.reshape(1, 36))[0], out)
+    assert e.value.code == P.EINVAL
+    b = np.zeros(36, np.uint8)
+    b[:8] = 1
+    b[8:15] = 2                            # 15 stones: 21 empty cells
+    with pytest.raises(P.PentagoError) as e:
+        P.pentago_eval_deep(P.boards_to_codes(b.reshape(1, 36))[0], out)
+    assert e.value.code == P.ERANGE
