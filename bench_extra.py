@@ -21,6 +21,9 @@
   slices         whole slices 35 and 34 (330 and 750 D4-minimal sections, 7.7
                  and 63 GB) over representatives: one batched launch, a
                  hipGraph replay, and one launch per section.
+  deep           one position each of 22, 20 and 18 stones solved from scratch
+                 (pentago_eval_deep: the DAG of 14, 16, 18 empty cells across
+                 the GPU, layers in HBM).
   symmetry       the table transform under each of the 7 non-trivial board
                  symmetries of the 36->35 section (6,288,640 entries), and
                  sweeps whose child is held only as its D4 representative
@@ -300,7 +303,8 @@ def symmetry(P, torch, stream, resident):
     return res
 
 
-NAMES = ("endgame_4096", "endgame_2p20", "layers", "serving", "serving_resident", "symmetry", "slices")
+NAMES = ("endgame_4096", "endgame_2p20", "layers", "serving", "serving_resident", "symmetry", "slices",
+         "deep")
 
 
 def slices(P, torch, stream):
@@ -351,6 +355,34 @@ def slices(P, torch, stream):
     return res
 
 
+def deep(P, torch, stream):
+    """One position of 22, 20 and 18 stones (14, 16, 18 empty cells) from
+    random legal play, each solved from scratch by pentago_eval_deep.
+    Algorithmic bytes: 64 B read per (node, child) edge + 64 B written per
+    node below the root."""
+    out = torch.zeros(8, dtype=torch.int64, device="cuda")
+    res = {}
+    for stones in (22, 20, 18):
+        b = I.random_play_boards(1, stones, stones, seed=I.SEED_SERVE + 50 + stones)[0]
+        codes = P.boards_to_codes(b.reshape(1, 36))[0]
+        e = 36 - stones
+        nodes = [math.comb(e, t) * math.comb(t, (t + 1) // 2) for t in range(e + 1)]
+        alg = 64 * sum(n * (e - t) for t, n in enumerate(nodes)) + 64 * sum(nodes[1:])
+        med, mn = _time(torch, stream, lambda: P.pentago_eval_deep(codes, out, stream), 5)
+        # the same root through the batched solver's layout limit: not
+        # comparable beyond 10 empty cells, so the check is the recurrence and
+        # symmetry tests; here the result must be stable across launches
+        first = out.clone()
+        P.pentago_eval_deep(codes, out, stream)
+        torch.cuda.synchronize()
+        res["empty%d" % e] = {"stones": stones, "dag_nodes": sum(nodes), "ms": med, "min_ms": mn,
+                              "nodes_per_s": sum(nodes) / (med * 1e-3),
+                              "algorithmic_GB_s": alg / (med * 1e-3) / 1e9,
+                              "frac_hbm": alg / (med * 1e-3) / 8e12,
+                              "repeatable": bool(torch.equal(first, out))}
+    return res
+
+
 def run_all(P, torch, stream, boards_2p20=None, serve_queries=None, resident=None, only=None):
     res = {}
     for name, fn in (("endgame_4096", lambda: endgame(P, torch, stream, I.random_placement_boards(4096, 17, 16), False)),
@@ -359,7 +391,8 @@ def run_all(P, torch, stream, boards_2p20=None, serve_queries=None, resident=Non
                      ("serving", lambda: serving(P, torch, stream, resident, serve_queries)),
                      ("serving_resident", lambda: serving_resident(P, torch, stream, resident, serve_queries)),
                      ("symmetry", lambda: symmetry(P, torch, stream, resident)),
-                     ("slices", lambda: slices(P, torch, stream))):
+                     ("slices", lambda: slices(P, torch, stream)),
+                     ("deep", lambda: deep(P, torch, stream))):
         if only is not None and name not in only:
             continue
         if name == "endgame_2p20" and boards_2p20 is None:
