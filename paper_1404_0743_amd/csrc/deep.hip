@@ -205,11 +205,25 @@ size_t deep_scratch_bytes(int e)
 
 }  // namespace pg
 
-using namespace pg;
+namespace pg {
 
-extern "C" int pentago_eval_deep(pentago_board board, pentago_superinfo *out, void *hip_stream)
+// Empty cells of a board (-1 for an invalid code).
+int board_empties(uint64_t packed)
 {
-    if (!out) return fail(PENTAGO_EINVAL, "out is NULL");
+    int e = 0;
+    for (int j = 0; j < 4; j++) {
+        int x = (int)((packed >> (16 * j)) & 0xffff);
+        if (x >= 19683) return -1;
+        for (int l = 0; l < 9; l++, x /= 3) e += x % 3 == 0;
+    }
+    return e;
+}
+
+// Enqueue the deep solve of one board (packed quadrant codes) on st.
+int eval_deep_enqueue(uint64_t packed, uint4 *out, hipStream_t st)
+{
+    pentago_board board;
+    for (int j = 0; j < 4; j++) board.q[j] = (uint16_t)((packed >> (16 * j)) & 0xffff);
     DevTables T;
     int rc = device_tables(&T);
     if (rc) return rc;
@@ -248,7 +262,6 @@ extern "C" int pentago_eval_deep(pentago_board board, pentago_superinfo *out, vo
     int dev = 0;
     hipError_t err = hipGetDevice(&dev);
     if (err != hipSuccess) return hip_fail(err, "hipGetDevice");
-    const hipStream_t st = (hipStream_t)hip_stream;
     if (dev < 64 && !binom_ready[dev]) {
         uint32_t tab[kDeepMaxEmpty + 2][kDeepMaxEmpty + 2];
         for (int n = 0; n < kDeepMaxEmpty + 2; n++)
@@ -267,7 +280,7 @@ extern "C" int pentago_eval_deep(pentago_board board, pentago_superinfo *out, vo
     if (err != hipSuccess) return hip_fail(err, "hipMallocAsync(deep scratch)");
     uint4 *buf[2] = {(uint4 *)base, (uint4 *)(base + (size_t)maxlayer * 64)};
     J.ftab = (uint4 *)(base + 2 * (size_t)maxlayer * 64);
-    J.out = (uint4 *)out;
+    J.out = out;
     int cur = 0;
     for (int t = e; t >= 0 && err == hipSuccess; t--) {
         J.t = t;
@@ -288,4 +301,16 @@ extern "C" int pentago_eval_deep(pentago_board board, pentago_superinfo *out, vo
     if (err != hipSuccess) return hip_fail(err, "deep endgame launch");
     (void)maxsub;
     return 0;
+}
+
+}  // namespace pg
+
+using namespace pg;
+
+extern "C" int pentago_eval_deep(pentago_board board, pentago_superinfo *out, void *hip_stream)
+{
+    if (!out) return fail(PENTAGO_EINVAL, "out is NULL");
+    const uint64_t packed = (uint64_t)board.q[0] | ((uint64_t)board.q[1] << 16) | ((uint64_t)board.q[2] << 32) |
+                            ((uint64_t)board.q[3] << 48);
+    return eval_deep_enqueue(packed, (uint4 *)out, (hipStream_t)hip_stream);
 }

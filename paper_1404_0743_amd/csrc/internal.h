@@ -37,6 +37,9 @@ void section_standardize(const pentago_section &s, pentago_section *rep, int *sy
 void set_child_syms(const pentago_section &s, const pentago_superinfo *const rep[4], SweepJob *J);
 int make_sym_job(const pentago_section &s, const pentago_superinfo *table, int sym,
                  pentago_superinfo *out, SymJob *J);
+int board_empties(uint64_t packed);
+size_t deep_scratch_bytes(int e);
+int eval_deep_enqueue(uint64_t packed, uint4 *out, hipStream_t st);
 int eval_grid(int *grid);
 size_t eval_scratch_bytes(size_t n, int grid, bool deep);
 int eval_enqueue(const uint64_t *boards, size_t n, uint4 *out, int *status, bool deep, int grid,

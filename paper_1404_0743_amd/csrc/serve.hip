@@ -50,9 +50,11 @@ struct Batch {
     hipEvent_t done = nullptr;
 };
 
-constexpr int kClasses = 5;
+constexpr int kClasses = 6;
 
-int class_of_empties(int e) { return e <= 6 ? 1 : e == 7 ? 2 : e == 8 ? 3 : 4; }
+// search classes by empty cells: 1 (<= 6), 2 (7), 3 (8), 4 (9-10) in batches
+// on the batched endgame solver, 5 (11-20) one at a time on the deep solver
+int class_of_empties(int e) { return e <= 6 ? 1 : e == 7 ? 2 : e == 8 ? 3 : e <= 10 ? 4 : 5; }
 
 }  // namespace
 
@@ -137,6 +139,8 @@ int launch_batch(pentago_server *S, int si, Batch &B)
         e = hipMemcpyAsync(S->d_sec[si], S->h_sec[si], n * 4, hipMemcpyHostToDevice, st);
         if (e == hipSuccess)
             e = launch_lookup(S->d_boards[si], S->d_sec[si], (int)n, S->d_secs, S->d_out[si], S->T, st);
+    } else if (e == hipSuccess && B.cls == 5) {
+        rc = eval_deep_enqueue(B.qs[0].board, S->d_out[si], st);
     } else if (e == hipSuccess) {
         // search classes 1..4 (empties <= 6, 7, 8, 9-10) -> endgame classes 2, 1, 0, 0
         const int ecls = B.cls == 1 ? 2 : B.cls == 2 ? 1 : 0;
@@ -187,8 +191,10 @@ void worker_loop(pentago_server *S)
                             best = c;
                 }
                 if (best < 0) continue;
-                const size_t take = std::min<size_t>(S->pending[best].size(), S->cfg.max_batch);
-                const size_t need = best == 0 ? 0 : eval_scratch_bytes(take, S->grid, best == 4);
+                const size_t take = best == 5 ? 1 : std::min<size_t>(S->pending[best].size(), S->cfg.max_batch);
+                const size_t need = best == 0   ? 0
+                                    : best == 5 ? deep_scratch_bytes(board_empties(S->pending[5].front().board))
+                                                : eval_scratch_bytes(take, S->grid, best == 4);
                 if (S->scratch_in_use + need > S->cfg.memory_budget && S->scratch_in_use > 0) continue;
                 B.cls = best;
                 S->class_running[best]++;
@@ -362,7 +368,7 @@ int pentago_serve_submit(pentago_server *srv, pentago_board board, uint64_t *tic
         q.cls = 0;
         q.sec = it->second;
     } else {
-        if (e > 10) return fail(PENTAGO_ERANGE, "more than 10 empty cells and no resident section");
+        if (e > 20) return fail(PENTAGO_ERANGE, "more than 20 empty cells and no resident section");
         q.cls = class_of_empties(e);
         q.sec = 0;
     }

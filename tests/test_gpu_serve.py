@@ -158,3 +158,26 @@ def test_lookups_through_board_symmetries(P, resident):
     srv.close()
     assert st["lookups"] == len(boards) and st["searches"] == 0
     assert np.array_equal(got, O.minimax_tables(boards))
+
+
+def test_deep_queries(P, resident):
+    """Boards with 11 to 14 empty cells are searched by the deep solver, one
+    at a time, next to ordinary searches and lookups; each answer equals the
+    deep solver called directly (itself checked against minimax, the batched
+    solver and the recurrence)."""
+    log("serve deep queries")
+    deep = I.random_play_boards(6, 22, 25, seed=91)
+    mixed = np.concatenate([deep, queries(20, 20, seed=92)])
+    codes = P.boards_to_codes(mixed)
+    srv = P.Server(memory_budget=1 << 30, max_inflight=4096, max_batch=64, streams=3)
+    srv.add_section(RESIDENT, resident)
+    got = run_all(P, srv, codes)
+    st = srv.stats()
+    srv.close()
+    assert st["queries"] == len(mixed) and st["lookups"] == 20
+    out = torch.zeros(8, dtype=torch.int64, device="cuda")
+    for k, c in enumerate(codes[:len(deep)]):
+        P.pentago_eval_deep(c, out)
+        torch.cuda.synchronize()
+        assert np.array_equal(got[k], out.cpu().numpy().view(np.uint64)), k
+    assert np.array_equal(got[len(deep):], O.minimax_tables(mixed[len(deep):]))
