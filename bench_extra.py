@@ -24,6 +24,8 @@
   deep           one position each of 22, 20 and 18 stones solved from scratch
                  (pentago_eval_deep: the DAG of 14, 16, 18 empty cells across
                  the GPU, layers in HBM).
+  serving_deep   32 positions with 18..22 stones submitted at once to the
+                 server, which runs them on the deep solver, three at a time.
   symmetry       the table transform under each of the 7 non-trivial board
                  symmetries of the 36->35 section (6,288,640 entries), and
                  sweeps whose child is held only as its D4 representative
@@ -304,7 +306,7 @@ def symmetry(P, torch, stream, resident):
 
 
 NAMES = ("endgame_4096", "endgame_2p20", "layers", "serving", "serving_resident", "symmetry", "slices",
-         "deep")
+         "deep", "serving_deep")
 
 
 def slices(P, torch, stream):
@@ -383,6 +385,34 @@ def deep(P, torch, stream):
     return res
 
 
+def serving_deep(P, torch, stream):
+    """Deep queries through the server: 32 positions with 18..22 stones (14
+    to 18 empty cells) from random legal play, all submitted at once; the
+    server runs them on the deep solver, one per search stream (3).  Latency p50/p99
+    from submission; a sample of answers against the deep solver called
+    directly."""
+    boards = I.random_play_boards(32, 18, 22, seed=I.SEED_SERVE + 60)
+    codes = P.boards_to_codes(boards)
+    srv = P.Server(memory_budget=8 << 30, max_inflight=1024, max_batch=64, streams=4)
+    srv.replay(codes[:2], np.zeros(2))
+    srv.reset_stats()
+    t0 = time.perf_counter()
+    got = srv.replay(codes, np.zeros(len(codes)))
+    dt = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    out = torch.zeros(8, dtype=torch.int64, device="cuda")
+    same = True
+    for k in range(0, len(codes), 8):
+        P.pentago_eval_deep(codes[k], out, stream)
+        torch.cuda.synchronize()
+        same = same and bool(np.array_equal(out.cpu().numpy().view(np.uint64), got[k]))
+    empties = 36 - (boards != 0).sum(axis=1)
+    return {"queries": int(st["queries"]), "searches": int(st["searches"]),
+            "empty_cells": [int(empties.min()), int(empties.max())], "queries_per_s": len(codes) / dt,
+            "p50_us": st["p50_us"], "p99_us": st["p99_us"], "answers_equal_deep_solver": same}
+
+
 def run_all(P, torch, stream, boards_2p20=None, serve_queries=None, resident=None, only=None):
     res = {}
     for name, fn in (("endgame_4096", lambda: endgame(P, torch, stream, I.random_placement_boards(4096, 17, 16), False)),
@@ -392,12 +422,13 @@ def run_all(P, torch, stream, boards_2p20=None, serve_queries=None, resident=Non
                      ("serving_resident", lambda: serving_resident(P, torch, stream, resident, serve_queries)),
                      ("symmetry", lambda: symmetry(P, torch, stream, resident)),
                      ("slices", lambda: slices(P, torch, stream)),
-                     ("deep", lambda: deep(P, torch, stream))):
+                     ("deep", lambda: deep(P, torch, stream)),
+                     ("serving_deep", lambda: serving_deep(P, torch, stream))):
         if only is not None and name not in only:
             continue
         if name == "endgame_2p20" and boards_2p20 is None:
             continue
-        if name.startswith("serving") and serve_queries is None:
+        if name in ("serving", "serving_resident") and serve_queries is None:
             continue
         t0 = time.perf_counter()
         try:

@@ -324,9 +324,9 @@ int pentago_serve_add_section(pentago_server *srv, pentago_section s,
 /* Submit one board.  EAGAIN when max_inflight queries are pending; EINVAL
  * for an invalid board; ERANGE for more than 20 empty cells on a board that
  * no resident section holds.  Searches with up to 10 empty cells run in
- * batches on the batched endgame solver; with 11 to 20, one at a time on the
- * deep solver (pentago_eval_deep), its scratch counted against the memory
- * budget like a batch's.  A batch is admitted when a stream is idle and
+ * batches on the batched endgame solver; with 11 to 20, one per batch on the
+ * deep solver (pentago_eval_deep), on every search stream at once, each
+ * one's scratch counted against the memory budget like a batch's.  A batch is admitted when a stream is idle and
  * its device scratch fits memory_budget next to the batches running (a
  * batch is always admitted when nothing runs, so no query waits forever).
  * Lookups are admitted before searches; with two or more streams the first

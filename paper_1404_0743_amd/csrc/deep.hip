@@ -20,6 +20,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
+#include <set>
 
 namespace pg {
 
@@ -258,23 +260,26 @@ int eval_deep_enqueue(uint64_t packed, uint4 *out, hipStream_t st)
         J.cm0[j] = J.mover == 1 ? bm[j] : wm[j];
         J.om0[j] = J.mover == 1 ? wm[j] : bm[j];
     }
-    static bool binom_ready[64] = {false};
     int dev = 0;
     hipError_t err = hipGetDevice(&dev);
     if (err != hipSuccess) return hip_fail(err, "hipGetDevice");
-    if (dev < 64 && !binom_ready[dev]) {
-        uint32_t tab[kDeepMaxEmpty + 2][kDeepMaxEmpty + 2];
-        for (int n = 0; n < kDeepMaxEmpty + 2; n++)
-            for (int k = 0; k < kDeepMaxEmpty + 2; k++) tab[n][k] = (uint32_t)binom_host(n, k);
-        err = hipMemcpyToSymbol(HIP_SYMBOL(c_binom), tab, sizeof(tab));
-        if (err != hipSuccess) return hip_fail(err, "binomial table upload");
-        binom_ready[dev] = true;
+    {
+        // the binomial table, once per device
+        static std::mutex mu;
+        static std::set<int> ready;
+        std::lock_guard<std::mutex> lock(mu);
+        if (!ready.count(dev)) {
+            uint32_t tab[kDeepMaxEmpty + 2][kDeepMaxEmpty + 2];
+            for (int n = 0; n < kDeepMaxEmpty + 2; n++)
+                for (int k = 0; k < kDeepMaxEmpty + 2; k++) tab[n][k] = (uint32_t)binom_host(n, k);
+            err = hipMemcpyToSymbol(HIP_SYMBOL(c_binom), tab, sizeof(tab));
+            if (err != hipSuccess) return hip_fail(err, "binomial table upload");
+            ready.insert(dev);
+        }
     }
-    uint64_t maxlayer = 0, maxsub = 0;
-    for (int t = 0; t <= e; t++) {
-        maxlayer = std::max(maxlayer, binom_host(e, t) * binom_host(t, (t + 1) / 2));
-        maxsub = std::max(maxsub, binom_host(e, (t + 1) / 2) + binom_host(e, t / 2));
-    }
+    keep_pool(dev);
+    uint64_t maxlayer = 0;
+    for (int t = 0; t <= e; t++) maxlayer = std::max(maxlayer, binom_host(e, t) * binom_host(t, (t + 1) / 2));
     char *base = nullptr;
     err = hipMallocAsync((void **)&base, deep_scratch_bytes(e), st);
     if (err != hipSuccess) return hip_fail(err, "hipMallocAsync(deep scratch)");
@@ -299,7 +304,6 @@ int eval_deep_enqueue(uint64_t packed, uint4 *out, hipStream_t st)
     }
     (void)hipFreeAsync(base, st);
     if (err != hipSuccess) return hip_fail(err, "deep endgame launch");
-    (void)maxsub;
     return 0;
 }
 

@@ -37,6 +37,8 @@ void section_standardize(const pentago_section &s, pentago_section *rep, int *sy
 void set_child_syms(const pentago_section &s, const pentago_superinfo *const rep[4], SweepJob *J);
 int make_sym_job(const pentago_section &s, const pentago_superinfo *table, int sym,
                  pentago_superinfo *out, SymJob *J);
+// Keep the device's stream-ordered allocations (hipMallocAsync) pooled.
+void keep_pool(int dev);
 int board_empties(uint64_t packed);
 size_t deep_scratch_bytes(int e);
 int eval_deep_enqueue(uint64_t packed, uint4 *out, hipStream_t st);

@@ -182,11 +182,13 @@ void worker_loop(pentago_server *S)
                 int best = -1;
                 if (!S->pending[0].empty()) best = 0;
                 else if (i > 0 || nst == 1) {
-                    // one batch in flight per search class: under load the
-                    // class's queue grows while its batch runs, so batches
-                    // grow with the load instead of fragmenting
+                    // one batch in flight per batched search class: under load
+                    // the class's queue grows while its batch runs, so batches
+                    // grow with the load instead of fragmenting; deep queries
+                    // (one per batch) run on every search stream at once, so
+                    // the small layers of one overlap the others' work
                     for (int c = 1; c < kClasses; c++)
-                        if (!S->pending[c].empty() && S->class_running[c] == 0 &&
+                        if (!S->pending[c].empty() && (c == 5 || S->class_running[c] == 0) &&
                             (best < 0 || S->pending[c].front().t_submit < S->pending[best].front().t_submit))
                             best = c;
                 }
