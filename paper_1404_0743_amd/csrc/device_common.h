@@ -154,6 +154,16 @@ __device__ __forceinline__ void quad_transpose(uint4 (&r)[4], int l)
 }
 
 
+// A 16-byte store that does not allocate in the caches, for results written
+// once and not read again by the kernel that writes them (streaming writes:
+// the lines go to HBM without displacing the inputs the kernel still reads).
+__device__ __forceinline__ void store_stream(uint4 *p, uint4 v)
+{
+    typedef unsigned v4u __attribute__((ext_vector_type(4)));
+    const v4u x = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(x, (v4u *)p);
+}
+
 // Clear n work-queue counters (a kernel, not a memset, so the sequence can
 // be captured in a graph).
 static __global__ void zero_counter_kernel(unsigned long long *c, int n)

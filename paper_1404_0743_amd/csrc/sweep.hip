@@ -600,7 +600,7 @@ __device__ __forceinline__ void sweep_tile(const SweepJob &J, const DevTables &T
                                   quad_perm<0xFF>(off)};
 #pragma unroll
         for (int p = 0; p < 4; p++)
-            if (g0 + 16 * p + q < nparents) J.out[4 * offs[p] + l4] = r[p];
+            if (g0 + 16 * p + q < nparents) store_stream(J.out + 4 * offs[p] + l4, r[p]);
     }
 }
 
