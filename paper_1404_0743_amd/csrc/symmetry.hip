@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(256) transform_kernel(SymJob J, DevTables T)
                                    quad_perm<0xFF>(doff)};
 #pragma unroll
         for (int p = 0; p < 4; p++)
-            if (r0 + 16 * p + qq < end) J.dst[4 * (size_t)doffs[p] + ql] = v[p];
+            if (r0 + 16 * p + qq < end) store_stream(J.dst + 4 * (size_t)doffs[p] + ql, v[p]);
     }
 }
 
