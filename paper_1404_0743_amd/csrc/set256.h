@@ -309,6 +309,17 @@ PG_HD void sym_apply(Set256 &x, const int h[4])
         negate_dim<1>(x);
         negate_dim<2>(x);
         negate_dim<3>(x);
+    } else if constexpr (SYM != 0) {
+        // a rotation by r turns every pattern without a symmetry of its own
+        // by h = r: then the shifts are compile-time
+        constexpr int r = SYM & 3;
+        if (h[0] == r && h[1] == r && h[2] == r && h[3] == r) {
+            x = shift_dim(x, 0, r);
+            x = shift_dim(x, 1, r);
+            x = shift_dim(x, 2, r);
+            x = shift_dim(x, 3, r);
+            return;
+        }
     }
     x = shift_dim(x, 0, h[0]);
     x = shift_dim(x, 1, h[1]);
