@@ -44,25 +44,27 @@ struct DeepJob {
     uint4 *out;                   // the root's W/N (t = 0)
 };
 
-__device__ __forceinline__ uint32_t colex_rank(unsigned mask)
+typedef uint32_t BinomRow[kDeepMaxEmpty + 2];
+
+__device__ __forceinline__ uint32_t colex_rank(unsigned mask, const BinomRow *bn)
 {
     uint32_t r = 0;
     int i = 0;
     while (mask) {
         const int c = __builtin_ctz(mask);
         mask &= mask - 1;
-        r += c_binom[c][i + 1];
+        r += bn[c][i + 1];
         i++;
     }
     return r;
 }
 
 // The subset of {0..n-1} with k elements and colex rank r.
-__device__ __forceinline__ unsigned colex_unrank(uint32_t r, int k, int n)
+__device__ __forceinline__ unsigned colex_unrank(uint32_t r, int k, int n, const BinomRow *bn)
 {
     unsigned mask = 0;
     for (int c = n - 1; c >= 0 && k > 0; c--) {
-        const uint32_t b = c_binom[c][k];
+        const uint32_t b = bn[c][k];
         if (r >= b) {
             mask |= 1u << c;
             r -= b;
@@ -99,11 +101,22 @@ __device__ __forceinline__ unsigned unpack_bits(unsigned m, unsigned within)
     return r;
 }
 
-__device__ __forceinline__ uint32_t node_index(unsigned cmask, unsigned omask, int e, int so)
+__device__ __forceinline__ uint32_t node_index(unsigned cmask, unsigned omask, int e, int so, const BinomRow *bn)
 {
     const unsigned all = (1u << e) - 1u;
     const unsigned free = all & ~cmask;
-    return colex_rank(cmask) * c_binom[e - __popc(cmask)][so] + colex_rank(pack_bits(omask, free));
+    return colex_rank(cmask, bn) * bn[e - __popc(cmask)][so] + colex_rank(pack_bits(omask, free), bn);
+}
+
+// The binomial table, copied to LDS by each workgroup: the lanes index it
+// with different values, and from LDS those reads cost a few cycles instead
+// of a dependent memory load each (the ranking loops chain them).
+__device__ __forceinline__ const BinomRow *lds_binom(BinomRow *sb)
+{
+    for (int k = threadIdx.x; k < (kDeepMaxEmpty + 2) * (kDeepMaxEmpty + 2); k += blockDim.x)
+        sb[k / (kDeepMaxEmpty + 2)][k % (kDeepMaxEmpty + 2)] = c_binom[k / (kDeepMaxEmpty + 2)][k % (kDeepMaxEmpty + 2)];
+    __syncthreads();
+    return sb;
 }
 
 // Five-set of every subset of the empty cells of the two sizes of layer t
@@ -111,11 +124,13 @@ __device__ __forceinline__ uint32_t node_index(unsigned cmask, unsigned omask, i
 // colex rank: each node then reads its two.
 __global__ void __launch_bounds__(256) deep_five_kernel(DeepJob J, DevTables T)
 {
+    __shared__ BinomRow sb[kDeepMaxEmpty + 2];
+    const BinomRow *bn = lds_binom(sb);
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= J.nsub_c + J.nsub_o) return;
     const bool mine = i < J.nsub_c;
     const int k = mine ? (J.t + 1) >> 1 : J.t >> 1;
-    const unsigned m = colex_unrank(mine ? i : i - J.nsub_c, k, J.e);
+    const unsigned m = colex_unrank(mine ? i : i - J.nsub_c, k, J.e, bn);
     unsigned xm[4];
 #pragma unroll
     for (int j = 0; j < 4; j++) xm[j] = mine ? J.cm0[j] : J.om0[j];
@@ -139,17 +154,19 @@ __global__ void __launch_bounds__(256) deep_five_kernel(DeepJob J, DevTables T)
 // five-sets, keep the terms its parents read (the root's W/N at t = 0).
 __global__ void __launch_bounds__(256) deep_node_kernel(DeepJob J, DevTables T)
 {
+    __shared__ BinomRow sb[kDeepMaxEmpty + 2];
+    const BinomRow *bn = lds_binom(sb);
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= J.nodes) return;
     const int e = J.e, t = J.t;
     const int sc = (t + 1) >> 1, so = t >> 1;
     const unsigned all = (1u << e) - 1u;
-    const uint32_t per = c_binom[e - sc][so];
+    const uint32_t per = bn[e - sc][so];
     const uint32_t r1 = i / per, r2 = i - r1 * per;
-    const unsigned cmask = colex_unrank(r1, sc, e);
-    const unsigned omask = unpack_bits(colex_unrank(r2, so, e - sc), all & ~cmask);
-    const Set256 Fc = set_from(J.ftab + 2 * (size_t)colex_rank(cmask));
-    const Set256 Fo = set_from(J.ftab + 2 * ((size_t)J.nsub_c + colex_rank(omask)));
+    const unsigned cmask = colex_unrank(r1, sc, e, bn);
+    const unsigned omask = unpack_bits(colex_unrank(r2, so, e - sc, bn), all & ~cmask);
+    const Set256 Fc = set_from(J.ftab + 2 * (size_t)colex_rank(cmask, bn));
+    const Set256 Fo = set_from(J.ftab + 2 * ((size_t)J.nsub_c + colex_rank(omask, bn)));
     const bool xroot = (t & 1) == 0;   // the side to move at layer t is the root's mover
     const Set256 &Fx = xroot ? Fc : Fo;
     const Set256 &Fy = xroot ? Fo : Fc;
@@ -164,7 +181,7 @@ __global__ void __launch_bounds__(256) deep_node_kernel(DeepJob J, DevTables T)
             const int sl = __builtin_ctz(f);
             f &= f - 1;
             const unsigned bit = 1u << sl;
-            const uint32_t ci = xroot ? node_index(cmask | bit, omask, e, cso) : node_index(cmask, omask | bit, e, cso);
+            const uint32_t ci = xroot ? node_index(cmask | bit, omask, e, cso, bn) : node_index(cmask, omask | bit, e, cso, bn);
             const uint4 *p = J.prev + 4 * (size_t)ci;
             s_or_into(Wnt, set_from(p));
             s_or_into(Nnt, set_from(p + 2));
