@@ -195,10 +195,10 @@ __global__ void __launch_bounds__(256) deep_node_kernel(DeepJob J, DevTables T)
         Set256 A, B;
         child_terms(Fy, W, N, A, B);
         uint4 *p = J.cur + 4 * (size_t)i;
-        store_stream(p, make_uint4(A.w[0], A.w[1], A.w[2], A.w[3]));
-        store_stream(p + 1, make_uint4(A.w[4], A.w[5], A.w[6], A.w[7]));
-        store_stream(p + 2, make_uint4(B.w[0], B.w[1], B.w[2], B.w[3]));
-        store_stream(p + 3, make_uint4(B.w[4], B.w[5], B.w[6], B.w[7]));
+        p[0] = make_uint4(A.w[0], A.w[1], A.w[2], A.w[3]);
+        p[1] = make_uint4(A.w[4], A.w[5], A.w[6], A.w[7]);
+        p[2] = make_uint4(B.w[0], B.w[1], B.w[2], B.w[3]);
+        p[3] = make_uint4(B.w[4], B.w[5], B.w[6], B.w[7]);
     }
 }
 

@@ -275,10 +275,10 @@ __device__ __forceinline__ void prep_entry(const SweepJob &J, const DevTables &T
     swap_with3_rt(A, J.d);
     swap_with3_rt(B, J.d);
     uint4 *p = J.prep_out[JD] + 4 * block_offset(cshape, idx.v);
-    store_stream(p, make_uint4(A.w[0], A.w[1], A.w[2], A.w[3]));
-    store_stream(p + 1, make_uint4(A.w[4], A.w[5], A.w[6], A.w[7]));
-    store_stream(p + 2, make_uint4(B.w[0], B.w[1], B.w[2], B.w[3]));
-    store_stream(p + 3, make_uint4(B.w[4], B.w[5], B.w[6], B.w[7]));
+    p[0] = make_uint4(A.w[0], A.w[1], A.w[2], A.w[3]);
+    p[1] = make_uint4(A.w[4], A.w[5], A.w[6], A.w[7]);
+    p[2] = make_uint4(B.w[0], B.w[1], B.w[2], B.w[3]);
+    p[3] = make_uint4(B.w[4], B.w[5], B.w[6], B.w[7]);
 }
 
 __device__ __forceinline__ long long prep_count(const SweepJob &J, int jd)
