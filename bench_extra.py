@@ -20,7 +20,9 @@
                  with random-play queries under Poisson arrivals.
   slices         whole slices 35 and 34 (330 and 750 D4-minimal sections, 7.7
                  and 63 GB) over representatives: one batched launch, a
-                 hipGraph replay, and one launch per section.
+                 hipGraph replay, and one launch per section; then 2^15
+                 positions of 34-35 stones answered by a server holding only
+                 those representatives.
   deep           one position each of 22, 20 and 18 stones solved from scratch
                  (pentago_eval_deep: the DAG of 14, 16, 18 empty cells across
                  the GPU, layers in HBM).
@@ -351,6 +353,31 @@ def slices(P, torch, stream):
             "graph_algorithmic_GB_s": alg / (t_graph * 1e-3) / 1e9,
             "graph_over_per_section": t_plain / t_graph, "same_bytes": bool(same)}
         del keep
+        if stones == 34:
+            # a server holding only the representatives of both slices answers
+            # every 34- and 35-stone position by lookup through a symmetry
+            boards = I.random_play_boards(1 << 15, 34, 35, seed=I.SEED_SERVE + 70)
+            codes = P.boards_to_codes(boards)
+            srv = P.Server(memory_budget=1 << 30, max_inflight=1 << 16, max_batch=4096, streams=4)
+            for tabs in (above, tables):
+                for counts, t in tabs.items():
+                    srv.add_section(counts, t)
+            srv.replay(codes[:1024], np.zeros(1024))
+            srv.reset_stats()
+            t0 = time.perf_counter()
+            got = srv.replay(codes, np.zeros(len(codes)))
+            dt = time.perf_counter() - t0
+            st = srv.stats()
+            srv.close()
+            dev = torch.from_numpy(codes[:4096].view(np.int16).copy()).cuda()
+            ref = torch.empty((4096, 8), dtype=torch.int64, device="cuda")
+            P.pentago_eval_batch(dev, ref, None, stream)
+            torch.cuda.synchronize()
+            res["lookups_from_slices"] = {
+                "resident_sections": len(above) + len(tables), "queries": int(st["queries"]),
+                "lookups": int(st["lookups"]), "queries_per_s": len(codes) / dt,
+                "p50_us": st["p50_us"], "p99_us": st["p99_us"],
+                "answers_equal_search": bool(np.array_equal(ref.cpu().numpy().view(np.uint64), got[:4096]))}
         above = tables
     del above
     torch.cuda.empty_cache()

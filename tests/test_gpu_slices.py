@@ -131,3 +131,24 @@ def test_slice35_plan_graph_replays(P, slices):
         torch.cuda.synchronize()
         assert all(torch.equal(tables[s], t35[s]) for s in tables), rep
     plan.close()
+
+
+def test_server_answers_whole_slices_from_representatives(P, slices):
+    """Every representative of slices 35 and 34 registered in a server:
+    any position with 34 or 35 stones is then a lookup (its section is an
+    image of a representative), and the answers equal the minimax search."""
+    from paper_1404_0743_amd import inputs as I
+    from test_gpu_serve import run_all
+    S, t35, t34 = slices
+    srv = P.Server(memory_budget=1 << 30, max_inflight=4096, max_batch=256, streams=3)
+    for tables in (t35, t34):
+        for counts, t in tables.items():
+            srv.add_section(counts, t)
+    boards = np.concatenate([I.random_play_boards(150, 35, 35, seed=351),
+                             I.random_play_boards(150, 34, 34, seed=341)])
+    log("whole-slice lookups", len(boards))
+    got = run_all(P, srv, P.boards_to_codes(boards))
+    st = srv.stats()
+    srv.close()
+    assert st["lookups"] == len(boards) and st["searches"] == 0
+    assert np.array_equal(got, O.minimax_tables(boards))
