@@ -149,3 +149,26 @@ def test_swap3_matches_definition():
                 c[d], c[3] = c[3], c[d]
                 want[sum(c[j] << (2 * j) for j in range(4))] = x[g]
             assert np.array_equal(got, want)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py runs on one GPU: --gpus N > 1 exits with a message (before
+    touching a GPU)."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--extra", "nonsense"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "unknown workloads" in r.stderr
+
+
+def test_section_image_and_standardize_errors():
+    with pytest.raises(P.PentagoError):
+        P.pentago_section_image(((5, 4), (4, 5), (5, 4), (4, 4)), 8)
+    with pytest.raises(P.PentagoError):
+        P.pentago_section_standardize(((9, 9), (0, 0), (0, 0), (0, 0)))
+    with pytest.raises(P.PentagoError):
+        P.pentago_slice_sections(37)
