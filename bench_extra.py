@@ -388,7 +388,8 @@ def deep(P, torch, stream):
     """One position of 22, 20 and 18 stones (14, 16, 18 empty cells) from
     random legal play, each solved from scratch by pentago_eval_deep.
     Algorithmic bytes: 64 B read per (node, child) edge + 64 B written per
-    node below the root."""
+    node below the root; half of that for the parity-halved form (32 B
+    records, the rotations of the board's own parity only)."""
     out = torch.zeros(8, dtype=torch.int64, device="cuda")
     res = {}
     for stones in (22, 20, 18):
@@ -404,11 +405,22 @@ def deep(P, torch, stream):
         first = out.clone()
         P.pentago_eval_deep(codes, out, stream)
         torch.cuda.synchronize()
+        # the parity-halved form (32 B records) for the board's own parity
+        # (g = 0): half the algorithmic bytes; its bits equal the full table's
+        half = torch.zeros(8, dtype=torch.int64, device="cuda")
+        hmed, hmn = _time(torch, stream, lambda: P.pentago_eval_deep_parity(codes, 0, half, stream), 5)
+        torch.cuda.synchronize()
+        hw = half.cpu().numpy().view(np.uint64)
+        fw = out.cpu().numpy().view(np.uint64)
         res["empty%d" % e] = {"stones": stones, "dag_nodes": sum(nodes), "ms": med, "min_ms": mn,
                               "nodes_per_s": sum(nodes) / (med * 1e-3),
                               "algorithmic_GB_s": alg / (med * 1e-3) / 1e9,
                               "frac_hbm": alg / (med * 1e-3) / 8e12,
-                              "repeatable": bool(torch.equal(first, out))}
+                              "repeatable": bool(torch.equal(first, out)),
+                              "parity_half_ms": hmed, "parity_half_min_ms": hmn,
+                              "parity_half_algorithmic_GB_s": alg / 2 / (hmed * 1e-3) / 1e9,
+                              "parity_half_within_full": bool(np.array_equal(hw & fw, hw)),
+                              "parity_half_bits": int(sum(bin(int(x)).count("1") for x in hw))}
     return res
 
 

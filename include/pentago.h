@@ -281,6 +281,18 @@ int pentago_eval_batch_grouped(const pentago_board *boards, size_t n, pentago_su
  * allocation fails. */
 int pentago_eval_deep(pentago_board board, pentago_superinfo *out, void *hip_stream);
 
+/* pentago_eval_deep for the rotations g of one parity of g0 + g1 + g2 + g3
+ * only (Section VIII: rmax flips that parity, so each layer needs the terms
+ * of one parity, alternating layer by layer, and its records shrink from 64
+ * to 32 B).  A board's own value sits at g = 0, of parity 0.
+ *   parity  0 or 1
+ *   out     device, 64 B: win/not-lose bits of parity `parity` equal to
+ *           pentago_eval_deep's; the bits of the other parity are zero.
+ * Scratch as for pentago_eval_deep at half the layer bytes (1.1 GB for
+ * e = 18, 3 GB for e = 20).  EINVAL for a parity other than 0 or 1, else the
+ * errors of pentago_eval_deep. */
+int pentago_eval_deep_parity(pentago_board board, int parity, pentago_superinfo *out, void *hip_stream);
+
 /* ---------------------------------------------------------------- serving */
 
 typedef struct pentago_server pentago_server;

@@ -42,7 +42,43 @@ struct DeepJob {
     const uint4 *prev;            // A/B records of layer t + 1
     uint4 *cur;                   // A/B records of layer t
     uint4 *out;                   // the root's W/N (t = 0)
+    int parity;                   // -1: all of L; 0 / 1: only the root's g with that parity of sum g_i
 };
+
+// Parity-halved records (Section VIII: rmax flips the parity of
+// g0 + g1 + g2 + g3, so a root's values of one parity need each layer's
+// terms of one parity only, alternating from layer to layer).  Bit
+// g0 + 4 g1 + 16 (g2 & 1) of word (g2 >> 1) + 2 g3 has parity
+// popcount(bit & 0x15) + g3 (mod 2); kEvenBits marks the even bits of the
+// words with g3 even (0, 1, 4, 5).  Words w and w ^ 2 differ in g3 by one,
+// so the bits of one parity of both fit one word: a 256-bit set of that
+// parity packs into 4 words, and a node's A/B record into 32 B.
+constexpr uint32_t kEvenBits = 0x5a5aa5a5u;
+
+// Mask of the bits of parity par in the words with g3 even.
+__device__ __forceinline__ uint32_t parity_bits(int par) { return par ? ~kEvenBits : kEvenBits; }
+
+// Pack the bits of parity par of x (words 0, 1, 4, 5 with 2, 3, 6, 7).
+__device__ __forceinline__ uint4 pack_parity(const Set256 &x, int par)
+{
+    const uint32_t m = parity_bits(par);
+    return make_uint4((x.w[0] & m) | (x.w[2] & ~m), (x.w[1] & m) | (x.w[3] & ~m), (x.w[4] & m) | (x.w[6] & ~m),
+                      (x.w[5] & m) | (x.w[7] & ~m));
+}
+
+// Unpack: both words of a pair take the packed word.  The bits of the other
+// parity then hold values of no meaning; every use below is bitwise per g or
+// goes through rmax, which reads them only for results of that other parity,
+// and those are dropped again when the next record is packed.
+__device__ __forceinline__ Set256 unpack_parity(uint4 v)
+{
+    Set256 x;
+    x.w[0] = x.w[2] = v.x;
+    x.w[1] = x.w[3] = v.y;
+    x.w[4] = x.w[6] = v.z;
+    x.w[5] = x.w[7] = v.w;
+    return x;
+}
 
 typedef uint32_t BinomRow[kDeepMaxEmpty + 2];
 
@@ -152,6 +188,8 @@ __global__ void __launch_bounds__(256) deep_five_kernel(DeepJob J, DevTables T)
 // One node of layer t per thread (Section II recurrence on Section III
 // tables): OR the children's prepared terms, combine with the node's own
 // five-sets, keep the terms its parents read (the root's W/N at t = 0).
+// HALF: records of 32 B holding one parity (the root's parity J.parity).
+template <bool HALF>
 __global__ void __launch_bounds__(256) deep_node_kernel(DeepJob J, DevTables T)
 {
     __shared__ BinomRow sb[kDeepMaxEmpty + 2];
@@ -182,15 +220,40 @@ __global__ void __launch_bounds__(256) deep_node_kernel(DeepJob J, DevTables T)
             f &= f - 1;
             const unsigned bit = 1u << sl;
             const uint32_t ci = xroot ? node_index(cmask | bit, omask, e, cso, bn) : node_index(cmask, omask | bit, e, cso, bn);
-            const uint4 *p = J.prev + 4 * (size_t)ci;
-            s_or_into(Wnt, set_from(p));
-            s_or_into(Nnt, set_from(p + 2));
+            if (HALF) {
+                const uint4 *p = J.prev + 2 * (size_t)ci;
+                s_or_into(Wnt, unpack_parity(p[0]));
+                s_or_into(Nnt, unpack_parity(p[1]));
+            } else {
+                const uint4 *p = J.prev + 4 * (size_t)ci;
+                s_or_into(Wnt, set_from(p));
+                s_or_into(Nnt, set_from(p + 2));
+            }
         }
     }
     Set256 W, N;
     combine(Fx, Fy, Wnt, Nnt, W, N);
     if (t == 0) {
+        if (HALF) {
+            // the root's entries of the other parity are cleared
+            const uint32_t m = parity_bits(J.parity);
+#pragma unroll
+            for (int w = 0; w < 8; w++) {
+                const uint32_t mw = (w & 2) ? ~m : m;
+                W.w[w] &= mw;
+                N.w[w] &= mw;
+            }
+        }
         store_info(J.out, W, N);
+    } else if (HALF) {
+        // a parent at parity p reads this record at p; layer t's records
+        // carry the root's parity for odd t and the other one for even t
+        Set256 A, B;
+        child_terms(Fy, W, N, A, B);
+        const int par = J.parity ^ ((t + 1) & 1);
+        uint4 *p = J.cur + 2 * (size_t)i;
+        p[0] = pack_parity(A, par);
+        p[1] = pack_parity(B, par);
     } else {
         Set256 A, B;
         child_terms(Fy, W, N, A, B);
@@ -211,15 +274,16 @@ static uint64_t binom_host(int n, int k)
 }
 
 // Device bytes the deep solver needs for a root with e empty cells: two
-// layers of 64 B records and the largest pair of five-set tables.
-size_t deep_scratch_bytes(int e)
+// layers of records (64 B, or 32 B when halved by parity) and the largest
+// pair of five-set tables.
+size_t deep_scratch_bytes(int e, bool half)
 {
     uint64_t layer = 0, sub = 0;
     for (int t = 0; t <= e; t++) {
         layer = std::max(layer, binom_host(e, t) * binom_host(t, (t + 1) / 2));
         sub = std::max(sub, binom_host(e, (t + 1) / 2) + binom_host(e, t / 2));
     }
-    return 2 * (size_t)layer * 64 + (size_t)sub * 32 + 256;
+    return 2 * (size_t)layer * (half ? 32 : 64) + (size_t)sub * 32 + 256;
 }
 
 }  // namespace pg
@@ -239,8 +303,9 @@ int board_empties(uint64_t packed)
 }
 
 // Enqueue the deep solve of one board (packed quadrant codes) on st.
-int eval_deep_enqueue(uint64_t packed, uint4 *out, hipStream_t st)
+int eval_deep_enqueue(uint64_t packed, uint4 *out, hipStream_t st, int parity)
 {
+    if (parity < -1 || parity > 1) return fail(PENTAGO_EINVAL, "parity must be 0 or 1");
     pentago_board board;
     for (int j = 0; j < 4; j++) board.q[j] = (uint16_t)((packed >> (16 * j)) & 0xffff);
     DevTables T;
@@ -273,6 +338,9 @@ int eval_deep_enqueue(uint64_t packed, uint4 *out, hipStream_t st)
     if (e > kDeepMaxEmpty) return fail(PENTAGO_ERANGE, "more than 20 empty cells");
     J.e = e;
     J.mover = nb == nw ? 1 : 2;
+    J.parity = parity;
+    const bool half = parity >= 0;
+    const size_t rec = half ? 32 : 64;
     for (int j = 0; j < 4; j++) {
         J.cm0[j] = J.mover == 1 ? bm[j] : wm[j];
         J.om0[j] = J.mover == 1 ? wm[j] : bm[j];
@@ -298,10 +366,10 @@ int eval_deep_enqueue(uint64_t packed, uint4 *out, hipStream_t st)
     uint64_t maxlayer = 0;
     for (int t = 0; t <= e; t++) maxlayer = std::max(maxlayer, binom_host(e, t) * binom_host(t, (t + 1) / 2));
     char *base = nullptr;
-    err = hipMallocAsync((void **)&base, deep_scratch_bytes(e), st);
+    err = hipMallocAsync((void **)&base, deep_scratch_bytes(e, half), st);
     if (err != hipSuccess) return hip_fail(err, "hipMallocAsync(deep scratch)");
-    uint4 *buf[2] = {(uint4 *)base, (uint4 *)(base + (size_t)maxlayer * 64)};
-    J.ftab = (uint4 *)(base + 2 * (size_t)maxlayer * 64);
+    uint4 *buf[2] = {(uint4 *)base, (uint4 *)(base + (size_t)maxlayer * rec)};
+    J.ftab = (uint4 *)(base + 2 * (size_t)maxlayer * rec);
     J.out = out;
     int cur = 0;
     for (int t = e; t >= 0 && err == hipSuccess; t--) {
@@ -315,7 +383,10 @@ int eval_deep_enqueue(uint64_t packed, uint4 *out, hipStream_t st)
         hipLaunchKernelGGL(deep_five_kernel, dim3((nsub + 255) / 256), dim3(256), 0, st, J, T);
         err = hipGetLastError();
         if (err != hipSuccess) break;
-        hipLaunchKernelGGL(deep_node_kernel, dim3((J.nodes + 255) / 256), dim3(256), 0, st, J, T);
+        if (half)
+            hipLaunchKernelGGL(deep_node_kernel<true>, dim3((J.nodes + 255) / 256), dim3(256), 0, st, J, T);
+        else
+            hipLaunchKernelGGL(deep_node_kernel<false>, dim3((J.nodes + 255) / 256), dim3(256), 0, st, J, T);
         err = hipGetLastError();
         cur ^= 1;
     }
@@ -334,4 +405,13 @@ extern "C" int pentago_eval_deep(pentago_board board, pentago_superinfo *out, vo
     const uint64_t packed = (uint64_t)board.q[0] | ((uint64_t)board.q[1] << 16) | ((uint64_t)board.q[2] << 32) |
                             ((uint64_t)board.q[3] << 48);
     return eval_deep_enqueue(packed, (uint4 *)out, (hipStream_t)hip_stream);
+}
+
+extern "C" int pentago_eval_deep_parity(pentago_board board, int parity, pentago_superinfo *out, void *hip_stream)
+{
+    if (!out) return fail(PENTAGO_EINVAL, "out is NULL");
+    if (parity != 0 && parity != 1) return fail(PENTAGO_EINVAL, "parity must be 0 or 1");
+    const uint64_t packed = (uint64_t)board.q[0] | ((uint64_t)board.q[1] << 16) | ((uint64_t)board.q[2] << 32) |
+                            ((uint64_t)board.q[3] << 48);
+    return eval_deep_enqueue(packed, (uint4 *)out, (hipStream_t)hip_stream, parity);
 }

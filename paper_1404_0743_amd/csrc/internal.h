@@ -40,8 +40,8 @@ int make_sym_job(const pentago_section &s, const pentago_superinfo *table, int s
 // Keep the device's stream-ordered allocations (hipMallocAsync) pooled.
 void keep_pool(int dev);
 int board_empties(uint64_t packed);
-size_t deep_scratch_bytes(int e);
-int eval_deep_enqueue(uint64_t packed, uint4 *out, hipStream_t st);
+size_t deep_scratch_bytes(int e, bool half = false);
+int eval_deep_enqueue(uint64_t packed, uint4 *out, hipStream_t st, int parity = -1);
 int eval_grid(int *grid);
 size_t eval_scratch_bytes(size_t n, int grid, bool deep);
 int eval_enqueue(const uint64_t *boards, size_t n, uint4 *out, int *status, bool deep, int grid,

@@ -83,6 +83,7 @@ _SIGS = {
     "pentago_plan_destroy": ([_P], ctypes.c_int),
     "pentago_eval_batch": ([_P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
     "pentago_eval_deep": ([Board, _P, _P], ctypes.c_int),
+    "pentago_eval_deep_parity": ([Board, ctypes.c_int, _P, _P], ctypes.c_int),
     "pentago_eval_batch_grouped": ([_P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
     "pentago_serve_create": ([_P, _P], ctypes.c_int),
     "pentago_serve_add_section": ([_P, Section, _P], ctypes.c_int),
@@ -351,6 +352,13 @@ def pentago_eval_deep(codes, out, stream=None):
     """One board (4 quadrant codes) solved from scratch; out: device tensor
     of 8 int64 (64 B)."""
     _check(lib().pentago_eval_deep(board(codes), _dev_ptr(out), _stream(stream)), "pentago_eval_deep")
+
+
+def pentago_eval_deep_parity(codes, parity, out, stream=None):
+    """pentago_eval_deep for the rotations of one parity of sum g_i (32 B
+    records per node); the other parity's bits of out are zero."""
+    _check(lib().pentago_eval_deep_parity(board(codes), int(parity), _dev_ptr(out), _stream(stream)),
+           "pentago_eval_deep_parity")
 
 
 def pentago_eval_batch(boards, out, status=None, stream=None, grouped=False):

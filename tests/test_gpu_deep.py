@@ -8,7 +8,9 @@ empty cells, and against the batched endgame solver (itself pinned to O2) for
 table follows from the tables of its placements by the Section II recurrence
 (checked bit by bit at 12 empty cells, every placement solved separately),
 and tables are carried into each other by the board symmetries (14 empty
-cells).  Full boards, boards showing fives, and argument errors."""
+cells).  The parity-halved form (32 B records) against minimax and against
+the full-table solver up to 18 empty cells.  Full boards, boards showing
+fives, and argument errors."""
 import sys
 
 import numpy as np
@@ -142,11 +144,76 @@ def test_full_boards_and_fives(P):
         assert np.array_equal(deep(P, b), want[k]), k
 
 
+def parity_masks():
+    """Per parity of g0 + g1 + g2 + g3, the 8 uint64 words of a W/N table
+    whose set bits are the rotations g of that parity (bit g0 + 4 g1 +
+    16 (g2 & 1) of 32-bit word (g2 >> 1) + 2 g3 of each 256-bit set; two
+    32-bit words per uint64, low word first; W then N)."""
+    words = [[0] * 8, [0] * 8]
+    for g in range(256):
+        g0, g1, g2, g3 = g & 3, (g >> 2) & 3, (g >> 4) & 3, g >> 6
+        words[(g0 + g1 + g2 + g3) & 1][(g2 >> 1) + 2 * g3] |= 1 << (g0 + 4 * g1 + 16 * (g2 & 1))
+    out = np.zeros((2, 8), np.uint64)
+    for par in range(2):
+        for j in range(4):
+            v = np.uint64(words[par][2 * j] | (words[par][2 * j + 1] << 32))
+            out[par, j] = v          # W
+            out[par, 4 + j] = v      # N
+    return out
+
+
+def deep_parity(P, board, par):
+    out = torch.full((8,), -1, dtype=torch.int64, device="cuda")   # every bit set: cleared bits show
+    P.pentago_eval_deep_parity(P.boards_to_codes(np.asarray(board).reshape(1, 36))[0], par, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint64)
+
+
+def test_parity_masks_split_l():
+    m = parity_masks()
+    assert int(np.bitwise_and(m[0], m[1]).sum()) == 0
+    assert all(int(x) == (1 << 64) - 1 for x in np.bitwise_or(m[0], m[1]))
+    assert sum(bin(int(x)).count("1") for x in m[0]) == 256   # 128 rotations x (W, N)
+
+
+def test_parity_halves_match_minimax(P):
+    """Section VIII parity halving: each half equals the minimax table (O2)
+    on the rotations of its parity and is zero on the others."""
+    m = parity_masks()
+    boards = I.random_play_boards(8, 32, 35, seed=78)
+    want = O.minimax_tables(boards)
+    for k, b in enumerate(boards):
+        for par in (0, 1):
+            log("deep parity vs minimax", k, par)
+            assert np.array_equal(deep_parity(P, b, par), want[k] & m[par]), (k, par)
+
+
+def test_parity_halves_match_full_solver(P):
+    """Both halves against the full-table solver, 6 to 18 empty cells; the
+    two halves together give the full table."""
+    m = parity_masks()
+    roots = [I.random_play_boards(1, 36 - e, 36 - e, seed=80 + e)[0] for e in (6, 9, 12, 15, 16, 18)]
+    for b in roots:
+        e = int((b == 0).sum())
+        full = deep(P, b)
+        halves = []
+        for par in (0, 1):
+            log("deep parity vs full, empties", e, "parity", par)
+            h = deep_parity(P, b, par)
+            assert np.array_equal(h, full & m[par]), (e, par)
+            halves.append(h)
+        assert np.array_equal(halves[0] | halves[1], full), e
+
+
 def test_errors(P):
     out = torch.zeros(8, dtype=torch.int64, device="cuda")
     with pytest.raises(P.PentagoError) as e:
         P.pentago_eval_deep((19683, 0, 0, 0), out)
     assert e.value.code == P.EINVAL
+    for par in (-1, 2):
+        with pytest.raises(P.PentagoError) as e:
+            P.pentago_eval_deep_parity((0, 0, 0, 0), par, out)
+        assert e.value.code == P.EINVAL
     b = np.zeros(36, np.uint8)
     b[[0, 1]] = 1                          # two black stones, no white: invalid counts
     with pytest.raises(P.PentagoError) as e:
