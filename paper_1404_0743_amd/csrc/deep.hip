@@ -110,20 +110,8 @@ __device__ __forceinline__ unsigned colex_unrank(uint32_t r, int k, int n, const
     return mask;
 }
 
-// Bits of m at the positions of `within`, packed (pext) and unpacked (pdep).
-__device__ __forceinline__ unsigned pack_bits(unsigned m, unsigned within)
-{
-    unsigned r = 0;
-    int i = 0;
-    while (within) {
-        const int c = __builtin_ctz(within);
-        within &= within - 1;
-        r |= ((m >> c) & 1u) << i;
-        i++;
-    }
-    return r;
-}
-
+// The k-th bit of m placed at the position of the k-th set bit of `within`
+// (pdep).
 __device__ __forceinline__ unsigned unpack_bits(unsigned m, unsigned within)
 {
     unsigned r = 0;
@@ -137,11 +125,19 @@ __device__ __forceinline__ unsigned unpack_bits(unsigned m, unsigned within)
     return r;
 }
 
-__device__ __forceinline__ uint32_t node_index(unsigned cmask, unsigned omask, int e, int so, const BinomRow *bn)
+// Colex rank of omask among the cells not in cmask (rank of the packed
+// subset): omask's cell c sits at c - popcount(cmask below c) among them.
+__device__ __forceinline__ uint32_t rank_in_free(unsigned omask, unsigned cmask, const BinomRow *bn)
 {
-    const unsigned all = (1u << e) - 1u;
-    const unsigned free = all & ~cmask;
-    return colex_rank(cmask, bn) * bn[e - __popc(cmask)][so] + colex_rank(pack_bits(omask, free), bn);
+    uint32_t r = 0;
+    int i = 0;
+    while (omask) {
+        const int c = __builtin_ctz(omask);
+        omask &= omask - 1;
+        r += bn[c - __popc(cmask & ((1u << c) - 1u))][i + 1];
+        i++;
+    }
+    return r;
 }
 
 // The binomial table, copied to LDS by each workgroup: the lanes index it
@@ -213,13 +209,19 @@ __global__ void __launch_bounds__(256) deep_node_kernel(DeepJob J, DevTables T)
         Nnt = s_full();
     } else {
         // children: the side to move puts a stone on a free cell
+        // child index rank(cmask') * C(e - |cmask'|, |omask'|) + rank of omask'
+        // among the cells not in cmask': cmask grows when the root's mover
+        // moves, else omask grows and cmask's rank is the same for all children
         const int cso = xroot ? so : so + 1;   // the other side's stones in layer t + 1
+        const uint32_t rc = colex_rank(cmask, bn);
+        const uint32_t per_c = xroot ? bn[e - sc - 1][cso] : bn[e - sc][cso];
         unsigned f = all & ~(cmask | omask);
         while (f) {
             const int sl = __builtin_ctz(f);
             f &= f - 1;
             const unsigned bit = 1u << sl;
-            const uint32_t ci = xroot ? node_index(cmask | bit, omask, e, cso, bn) : node_index(cmask, omask | bit, e, cso, bn);
+            const uint32_t ci = xroot ? colex_rank(cmask | bit, bn) * per_c + rank_in_free(omask, cmask | bit, bn)
+                                      : rc * per_c + rank_in_free(omask | bit, cmask, bn);
             if (HALF) {
                 const uint4 *p = J.prev + 2 * (size_t)ci;
                 s_or_into(Wnt, unpack_parity(p[0]));
