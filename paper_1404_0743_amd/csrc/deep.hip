@@ -199,7 +199,8 @@ __global__ void __launch_bounds__(256) deep_node_kernel(DeepJob J, DevTables T)
     const uint32_t r1 = i / per, r2 = i - r1 * per;
     const unsigned cmask = colex_unrank(r1, sc, e, bn);
     const unsigned omask = unpack_bits(colex_unrank(r2, so, e - sc, bn), all & ~cmask);
-    const Set256 Fc = set_from(J.ftab + 2 * (size_t)colex_rank(cmask, bn));
+    // (cmask was unranked from r1, so r1 is its colex rank)
+    const Set256 Fc = set_from(J.ftab + 2 * (size_t)r1);
     const Set256 Fo = set_from(J.ftab + 2 * ((size_t)J.nsub_c + colex_rank(omask, bn)));
     const bool xroot = (t & 1) == 0;   // the side to move at layer t is the root's mover
     const Set256 &Fx = xroot ? Fc : Fo;
@@ -213,7 +214,7 @@ __global__ void __launch_bounds__(256) deep_node_kernel(DeepJob J, DevTables T)
         // among the cells not in cmask': cmask grows when the root's mover
         // moves, else omask grows and cmask's rank is the same for all children
         const int cso = xroot ? so : so + 1;   // the other side's stones in layer t + 1
-        const uint32_t rc = colex_rank(cmask, bn);
+        const uint32_t rc = r1;
         const uint32_t per_c = xroot ? bn[e - sc - 1][cso] : bn[e - sc][cso];
         unsigned f = all & ~(cmask | omask);
         while (f) {
