@@ -172,3 +172,13 @@ def test_section_image_and_standardize_errors():
         P.pentago_section_standardize(((9, 9), (0, 0), (0, 0), (0, 0)))
     with pytest.raises(P.PentagoError):
         P.pentago_slice_sections(37)
+
+
+def test_deep_parity_argument_errors():
+    """pentago_eval_deep_parity rejects a NULL output and a parity other than
+    0 or 1 before any device work (the pointer below is never dereferenced)."""
+    import ctypes
+    assert P.lib().pentago_eval_deep_parity(P.board((0, 0, 0, 0)), 0, None, None) == P.EINVAL
+    for par in (-1, 2):
+        rc = P.lib().pentago_eval_deep_parity(P.board((0, 0, 0, 0)), par, ctypes.c_void_p(64), None)
+        assert rc == P.EINVAL
