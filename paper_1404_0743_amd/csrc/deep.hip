@@ -216,19 +216,33 @@ __global__ void __launch_bounds__(256) deep_node_kernel(DeepJob J, DevTables T)
         const int cso = xroot ? so : so + 1;   // the other side's stones in layer t + 1
         const uint32_t rc = r1;
         const uint32_t per_c = xroot ? bn[e - sc - 1][cso] : bn[e - sc][cso];
-        unsigned f = all & ~(cmask | omask);
-        while (f) {
-            const int sl = __builtin_ctz(f);
-            f &= f - 1;
+        auto child_index = [&](int sl) -> uint32_t {
             const unsigned bit = 1u << sl;
-            const uint32_t ci = xroot ? colex_rank(cmask | bit, bn) * per_c + rank_in_free(omask, cmask | bit, bn)
-                                      : rc * per_c + rank_in_free(omask | bit, cmask, bn);
+            return xroot ? colex_rank(cmask | bit, bn) * per_c + rank_in_free(omask, cmask | bit, bn)
+                         : rc * per_c + rank_in_free(omask | bit, cmask, bn);
+        };
+        // Every node of the layer has e - t free cells.  With 32 B records two
+        // children go per step, both loads issued before either is used (an
+        // odd count repeats the last child, which OR absorbs); with 64 B
+        // records the pair's registers would cost occupancy, so one per step.
+        const int nch = e - t;
+        unsigned f = all & ~(cmask | omask);
+        for (int k = 0; k < nch; k += HALF ? 2 : 1) {
+            const int sa = __builtin_ctz(f);
+            f &= f - 1;
+            const uint32_t ca = child_index(sa);
             if (HALF) {
-                const uint4 *p = J.prev + 2 * (size_t)ci;
-                s_or_into(Wnt, unpack_parity(p[0]));
-                s_or_into(Nnt, unpack_parity(p[1]));
+                const int sb = k + 1 < nch ? __builtin_ctz(f) : sa;
+                f &= f - 1;
+                const uint32_t cb = child_index(sb);
+                const uint4 *pa = J.prev + 2 * (size_t)ca, *pb = J.prev + 2 * (size_t)cb;
+                const uint4 a0 = pa[0], a1 = pa[1], b0 = pb[0], b1 = pb[1];
+                s_or_into(Wnt, unpack_parity(a0));
+                s_or_into(Nnt, unpack_parity(a1));
+                s_or_into(Wnt, unpack_parity(b0));
+                s_or_into(Nnt, unpack_parity(b1));
             } else {
-                const uint4 *p = J.prev + 4 * (size_t)ci;
+                const uint4 *p = J.prev + 4 * (size_t)ca;
                 s_or_into(Wnt, set_from(p));
                 s_or_into(Nnt, set_from(p + 2));
             }
