@@ -8,7 +8,9 @@ GPU before the timed region.  Inputs are resident in HBM when timing starts.
 
 Prints one JSON line: throughput in positions/s, the roofline of the sweep
 kernel (algorithmic bytes over HIP-event time on the launch stream) and the
-CPU oracle timed on a bounded sample of the same section.
+CPU oracle timed on a bounded sample of the same section.  The timed
+launches' output is compared bit for bit with the oracle's tables of that
+sample (``parity``); a mismatch exits with status 1.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra] [--extra a,b]
 """
@@ -33,28 +35,79 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    """What the host offers: logical CPUs, the CPUs this process may run on,
+    the thread count the box grants (OMP_NUM_THREADS) and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS")
+    threads = affinity
+    if omp and omp.isdigit() and int(omp) > 0:
+        threads = min(threads, int(omp))
+    return {"nproc": os.cpu_count(), "affinity": affinity, "omp_num_threads": omp, "model": model,
+            "threads": max(1, threads)}
+
+
 def cpu_baseline(entries, positions, seconds_target=15.0):
     """The oracle (O4, per-entry plain retrograde) on a bounded random sample
-    of the section's entries, on the host cores; scaled to positions/s."""
+    of the section's entries, on every host thread this process is granted,
+    and on one thread; scaled to positions/s.  Returns the baseline record,
+    the sampled blocked offsets and the oracle's tables for them (the
+    parity check of the timed output reuses them)."""
     import oracle as O
-    threads = min(16, os.cpu_count() or 1)
+    cpu = host_cpu()
+    threads = cpu["threads"]
     rng = np.random.default_rng(12345)
-    shape = O.section_shape(SECTION)
-    # calibrate on a small sample, then size the main sample to ~seconds_target
-    n = 256
+    all_idx = O.section_all_indices(SECTION)
+    pos_per_entry = positions / entries
+    # one thread, ~3 s
+    n1 = 512
     while True:
-        idx = np.stack([rng.integers(0, m, n) for m in shape], axis=1).astype(np.int32)
+        offs1 = rng.choice(entries, n1, replace=False)
         t0 = time.perf_counter()
-        O.section_solve(SECTION, [None] * 4, idx, nthreads=threads)
+        O.section_solve(SECTION, [None] * 4, all_idx[offs1], nthreads=1)
+        dt1 = time.perf_counter() - t0
+        if dt1 > 1.5 or n1 >= 1 << 16:
+            break
+        n1 = int(n1 * min(8.0, max(2.0, 3.0 / max(dt1, 1e-3))))
+    # all granted threads: calibrate, then size the sample to ~seconds_target
+    n = 4096
+    while True:
+        offs = np.sort(rng.choice(entries, n, replace=False))
+        t0 = time.perf_counter()
+        want = O.section_solve(SECTION, [None] * 4, all_idx[offs], nthreads=threads)
         dt = time.perf_counter() - t0
-        if dt > 2.0 or n >= 1 << 20:
+        if dt > seconds_target / 4 or n >= 1 << 21:
             break
         n = int(n * min(8.0, max(2.0, seconds_target / max(dt, 1e-3))))
-    pos_per_entry = positions / entries
-    return {"value": n * pos_per_entry / dt, "unit": "positions/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "%d random entries of the section (%.0f positions), plain per-entry "
-                      "retrograde on concrete boards, %d threads, %.1f s" % (n, n * pos_per_entry, threads, dt)}
+    rec = {"value": n * pos_per_entry / dt, "unit": "positions/s", "cores": threads,
+           "kind": "oracle",
+           "sample": "%d random entries of the section (%.0f positions), plain per-entry "
+                     "retrograde on concrete boards, %d threads, %.1f s" % (n, n * pos_per_entry, threads, dt),
+           "single_thread": {"value": n1 * pos_per_entry / dt1, "unit": "positions/s",
+                             "sample": "%d random entries, 1 thread, %.1f s" % (n1, dt1)},
+           "host": cpu}
+    return rec, offs, want
+
+
+def parity_sample(entries, n=4096):
+    """Oracle tables of n random entries of the section (blocked offsets)."""
+    import oracle as O
+    rng = np.random.default_rng(54321)
+    all_idx = O.section_all_indices(SECTION)
+    offs = np.sort(rng.choice(entries, n, replace=False))
+    return offs, O.section_solve(SECTION, [None] * 4, all_idx[offs], nthreads=host_cpu()["threads"])
 
 
 def _blob_sha(path):
@@ -207,6 +260,9 @@ def main():
                       "sweep_median_single": float(np.median(kernel_ms)),
                       "terminal_child_section": terminal_ms},
     }
+    # the timed launches' output, kept on the host for the parity check
+    # against the oracle below (a 402 MB copy, after the timed region)
+    out_host = out.cpu().numpy().view(np.uint64)
     if not args.no_extra:
         import bench_extra
         out_keep, child_keep = out, child
@@ -214,8 +270,20 @@ def main():
         res["extra"] = bench_extra.run_all(P, torch, stream, boards_2p20, serve_queries, resident, only)
     if not args.no_cpu:
         log("timing the CPU oracle on a sample ...")
-        res["cpu_baseline"] = cpu_baseline(entries, positions)
+        res["cpu_baseline"], offs, want = cpu_baseline(entries, positions)
+    else:
+        offs, want = parity_sample(entries)
+    # the timed launches' output against the oracle, bit for bit, on the
+    # sampled entries (their blocked offsets)
+    got = out_host[offs]
+    bad = int((got != want).any(axis=1).sum())
+    res["parity"] = {"entries_checked": int(len(offs)), "bit_exact": bad == 0, "mismatches": bad,
+                     "oracle": "O4, plain per-entry retrograde on concrete boards, 36-stone children "
+                               "evaluated directly"}
     print(json.dumps(res), flush=True)
+    if bad:
+        log("PARITY FAILURE: %d of %d sampled entries differ from the oracle" % (bad, len(offs)))
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -274,9 +274,9 @@ int pentago_eval_batch_grouped(const pentago_board *boards, size_t n, pentago_su
  * e empty cells in alternating colours; 86,574,831 nodes for e = 18) is
  * solved layer by layer across the whole GPU, two layers at a time in HBM.
  *   out   device, 64 B.
- * Device scratch (two layers of 64 B records: 2.2 GB for e = 18, 6 GB for
- * e = 20) is allocated stream-ordered on hip_stream and released after the
- * call's work.  Stream-ordered and asynchronous.  EINVAL for invalid codes or
+ * Device scratch (two layers of 64 B records, 2 x max_t C(e,t) C(t,ceil(t/2))
+ * x 64 B, plus the five-set table: 2.2 GB for e = 18, 17.0 GB for e = 20) is
+ * allocated stream-ordered on hip_stream and released after the call's work.  Stream-ordered and asynchronous.  EINVAL for invalid codes or
  * stone counts; ERANGE for more than 20 empty cells; EDEVICE when the scratch
  * allocation fails. */
 int pentago_eval_deep(pentago_board board, pentago_superinfo *out, void *hip_stream);
@@ -288,8 +288,8 @@ int pentago_eval_deep(pentago_board board, pentago_superinfo *out, void *hip_str
  *   parity  0 or 1
  *   out     device, 64 B: win/not-lose bits of parity `parity` equal to
  *           pentago_eval_deep's; the bits of the other parity are zero.
- * Scratch as for pentago_eval_deep at half the layer bytes (1.1 GB for
- * e = 18, 3 GB for e = 20).  EINVAL for a parity other than 0 or 1, else the
+ * Scratch as for pentago_eval_deep at half the layer bytes (32 B records:
+ * 1.1 GB for e = 18, 8.5 GB for e = 20).  EINVAL for a parity other than 0 or 1, else the
  * errors of pentago_eval_deep. */
 int pentago_eval_deep_parity(pentago_board board, int parity, pentago_superinfo *out, void *hip_stream);
 

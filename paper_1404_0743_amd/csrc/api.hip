@@ -218,6 +218,15 @@ int make_job(const pentago_section &s, const pentago_superinfo *const child[4],
         uint64_t entries = 1;
         for (int j = 0; j < 4; j++) entries *= (uint64_t)J->m[j];
         if (entries >= (1ull << 32)) return fail(PENTAGO_ERANGE, "sections of 2^32 entries or more are not supported");
+        // out must not overlap a child table the sweep reads
+        const uintptr_t o0 = (uintptr_t)out, o1 = o0 + 64 * entries;
+        for (int j = 0; j < 4; j++) {
+            if (!J->child[j]) continue;
+            const uint64_t centries = entries / (uint64_t)J->m[j] * (uint64_t)J->cm[j];
+            const uintptr_t c0 = (uintptr_t)J->child[j], c1 = c0 + 64 * centries;
+            if (o0 < c1 && c0 < o1)
+                return fail(PENTAGO_EINVAL, "out overlaps the child table of quadrant " + std::to_string(j));
+        }
     }
     if (force_d >= 0 && ((J->emask >> force_d) & 1)) best = force_d;
     J->d = best >= 0 ? best : 3;

@@ -197,7 +197,9 @@ void worker_loop(pentago_server *S)
                 const size_t need = best == 0   ? 0
                                     : best == 5 ? deep_scratch_bytes(board_empties(S->pending[5].front().board))
                                                 : eval_scratch_bytes(take, S->grid, best == 4);
-                if (S->scratch_in_use + need > S->cfg.memory_budget && S->scratch_in_use > 0) continue;
+                // lookups hold no scratch: the budget never holds them back
+                if (need > 0 && S->scratch_in_use + need > S->cfg.memory_budget && S->scratch_in_use > 0)
+                    continue;
                 B.cls = best;
                 S->class_running[best]++;
                 B.qs.assign(S->pending[best].begin(), S->pending[best].begin() + take);

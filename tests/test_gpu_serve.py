@@ -53,7 +53,7 @@ def queries(n_lookup, n_search, seed):
     for _ in range(n_lookup):
         b = O.section_board(RESIDENT, [rng.integers(0, m) for m in shape])
         look.append(O.apply(b, int(rng.integers(0, 256))))
-    search = I.random_play_boards(n_search, 29, 34, seed=seed)
+    search = I.random_play_boards(n_search, 29, 34, seed=seed) if n_search else np.zeros((0, 36), np.uint8)
     boards = np.concatenate([np.array(look).reshape(-1, 36), search])
     perm = rng.permutation(len(boards))
     return boards[perm]
@@ -181,3 +181,36 @@ def test_deep_queries(P, resident):
         torch.cuda.synchronize()
         assert np.array_equal(got[k], out.cpu().numpy().view(np.uint64)), k
     assert np.array_equal(got[len(deep):], O.minimax_tables(mixed[len(deep):]))
+
+
+def test_lookups_do_not_wait_behind_a_deep_search(P, resident):
+    """A 1 GiB budget with a 20-empty query running on the deep solver (about
+    17 GB of scratch, admitted because nothing else runs): lookups hold no
+    scratch, so the budget must not hold them back; they are all answered
+    while the deep search is still running, and their answers equal the
+    oracle's."""
+    log("serve lookups beside a deep search")
+    deep = I.random_play_boards(1, 16, 16, seed=93)
+    look = queries(64, 0, seed=94)
+    srv = P.Server(memory_budget=1 << 30, max_inflight=4096, max_batch=64, streams=2)
+    srv.add_section(RESIDENT, resident)
+    td = srv.submit(P.boards_to_codes(deep)[0])
+    assert td is not None
+    # the deep query is admitted first (it is alone), then the lookups arrive
+    tl = [srv.submit(c) for c in P.boards_to_codes(look)]
+    assert all(t is not None for t in tl)
+    got = []
+    for t in tl:
+        while True:
+            r = srv.poll(t)
+            if r is not None:
+                got.append(r)
+                break
+    deep_still_running = srv.poll(td) is None
+    while srv.poll(td) is None:
+        pass
+    st = srv.stats()
+    srv.close()
+    assert st["lookups"] == 64 and st["searches"] == 1
+    assert deep_still_running, "the lookups waited for the deep search"
+    assert np.array_equal(np.array(got), O.minimax_tables(look))

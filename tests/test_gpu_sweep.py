@@ -194,3 +194,25 @@ def test_errors(P):
     with pytest.raises(P.PentagoError) as e:
         P.pentago_solve_section(((7, 1), (2, 7), (1, 8), (8, 2)), [None] * 4, out)
     assert e.value.code == P.EINVAL
+
+
+def test_out_overlapping_a_child_is_rejected(P):
+    """out must not overlap a child table the sweep reads: EINVAL, and
+    nothing is launched (the buffer keeps its contents)."""
+    counts = ((7, 2), (2, 7), (1, 7), (8, 1))
+    cc = O.child_counts(counts, 2)
+    nc, n = O.section_entries(cc), O.section_entries(counts)
+    buf = torch.full((nc + n, 8), 7, dtype=torch.int64, device="cuda")
+    child = buf[:nc]
+    for start in (0, nc // 2, nc - 1):
+        with pytest.raises(P.PentagoError) as e:
+            P.pentago_solve_section(counts, [None, None, child, None], buf[start:start + n])
+        assert e.value.code == P.EINVAL
+    torch.cuda.synchronize()
+    assert bool((buf == 7).all())
+    # adjacent, not overlapping: accepted
+    P.pentago_solve_section(cc, [None] * 4, child)
+    P.pentago_solve_section(counts, [None, None, child, None], buf[nc:nc + n])
+    torch.cuda.synchronize()
+    want = O.section_solve(counts, [None] * 4)
+    assert np.array_equal(from_dev(buf[nc:nc + n]), want)
