@@ -267,6 +267,27 @@ int pentago_eval_batch(const pentago_board *boards, size_t n, pentago_superinfo 
 int pentago_eval_batch_grouped(const pentago_board *boards, size_t n, pentago_superinfo *out,
                                int32_t *status, void *hip_stream);
 
+/* Prepare the library on the current device: upload its read-only tables
+ * (about 0.3 MB, once per device; every other call does this itself on first
+ * use) and resolve the address of the fixed scratch array of
+ * pentago_eval_batch_noalloc on this device.  Allocates.  Idempotent;
+ * callers of the allocation-free call run it once per device beforehand. */
+int pentago_init(void);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc):
+ * pentago_eval_batch with no allocation of any kind.  Same arguments, same
+ * results, same kernels.  Its scratch (binning arrays, queue counters and the
+ * DAG layer slots of roots with 9 or 10 empty cells) is one fixed device array
+ * of 39,649,792 bytes per device, held until the process ends and shared by
+ * every call on that device: it keeps the last call's contents, and calls
+ * that overlap on one device (on different streams or threads) race; the
+ * caller serialises them.  Roots with 9 or 10 empty cells are solved by at
+ * most 64 workgroups at a time.  ERANGE for n > 2^20 (before any device
+ * work); EINVAL if pentago_init has not run on the current device. */
+int pentago_eval_batch_noalloc(const pentago_board *boards, size_t n, pentago_superinfo *out,
+                               int32_t *status, void *hip_stream);
+
 /* Exact superinfo of one deep position, solved to the full board over all
  * 256 quadrant rotations (Section VIII: positions outside the database are
  * solved from scratch; the paper's serial solver evaluates an 18-stone

@@ -111,6 +111,17 @@ int device_tables(DevTables *out)
     return 0;
 }
 
+int device_tables_ready(DevTables *out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    std::lock_guard<std::mutex> lock(g_dev_mutex);
+    auto it = g_dev_tables.find(dev);
+    if (it == g_dev_tables.end()) return -1;
+    *out = it->second;
+    return 0;
+}
+
 // ---------------------------------------------------------------------------
 // Sections
 // ---------------------------------------------------------------------------

@@ -262,7 +262,9 @@ __global__ void zero_ints_kernel(int *p, int n)
 // launches follow one another on the stream, one per LDS class, each taking
 // roots from its own device work queue (no host synchronisation):
 //   class 0: 8 to 10 empty cells, a workgroup per root (9 and 10 keep their
-//            layers in the workgroup's slot of a global buffer);
+//            layers in the workgroup's slot of a global buffer; only the
+//            first `slots` workgroups own a slot: they take the 9-10 queue
+//            first, then join the others on the 8-empty queue);
 //   class 1: 7 empty cells, a workgroup per root, a smaller LDS footprint;
 //   class 2: up to kWaveMaxEmpties, one wave per root, four per workgroup,
 //            synchronised per wave only.
@@ -273,7 +275,7 @@ constexpr int kWaveLdsBytes = 2 * 90 * 64 + 2 * 20 * 32;
 template <int CLS>
 __global__ void __launch_bounds__(256)
     eval_persistent_kernel(const uint64_t *boards, const int *order, const int *start,
-                           unsigned long long *counter, uint4 *out, uint4 *gl, DevTables T)
+                           unsigned long long *counter, uint4 *out, uint4 *gl, int slots, DevTables T)
 {
     extern __shared__ uint4 lds[];
     __shared__ long long s_item;
@@ -282,22 +284,35 @@ __global__ void __launch_bounds__(256)
     const int lo = CLS == 0 ? 0 : CLS == 1 ? start[7] : start[kWaveMaxEmpties];
     const int hi = CLS == 0 ? start[7] : CLS == 1 ? start[kWaveMaxEmpties] : start[11];
     if (CLS < 2) {
-        const int big = start[8];  // roots with 9 or 10 empty cells: [0, big)
-        uint4 *mine = gl + (size_t)blockIdx.x * 2 * 4 * kDagGlobalLayer;
+        // class 0: roots with 9 or 10 empty cells, [0, big), come from queue 3
+        // and only go to workgroups that own a global layer slot; the rest of
+        // the class, [big, hi), from queue 0.  Class 1 uses queue 1 only.
+        const int big = CLS == 0 ? start[8] : lo;
+        if (CLS == 0 && (int)blockIdx.x < slots) {
+            uint4 *mine = gl + (size_t)blockIdx.x * 2 * 4 * kDagGlobalLayer;
+            for (;;) {
+                if (threadIdx.x == 0) s_item = (long long)atomicAdd(&counter[3], 1ull);
+                __syncthreads();
+                const long long item = s_item;
+                __syncthreads();
+                if (item >= big) break;
+                const int root = order[item];
+                const RootInfo R = decode_root(boards[root]);
+                solve_root<256>(R, T, mine, mine + 4 * kDagGlobalLayer, lds, out + 4 * (size_t)root,
+                                s_slots[0][0], s_slots[0][1]);
+                __syncthreads();
+            }
+        }
         for (;;) {
             if (threadIdx.x == 0) s_item = (long long)atomicAdd(&counter[CLS], 1ull);
             __syncthreads();
-            const long long item = lo + s_item;
+            const long long item = big + s_item;
             __syncthreads();
             if (item >= hi) break;
             const int root = order[item];
             const RootInfo R = decode_root(boards[root]);
-            if (CLS == 0 && item < big)
-                solve_root<256>(R, T, mine, mine + 4 * kDagGlobalLayer, lds, out + 4 * (size_t)root,
-                                s_slots[0][0], s_slots[0][1]);
-            else
-                solve_root<256>(R, T, lds, lds + 4 * T.dag_max[R.e], lds + 8 * T.dag_max[R.e],
-                                out + 4 * (size_t)root, s_slots[0][0], s_slots[0][1]);
+            solve_root<256>(R, T, lds, lds + 4 * T.dag_max[R.e], lds + 8 * T.dag_max[R.e],
+                            out + 4 * (size_t)root, s_slots[0][0], s_slots[0][1]);
             __syncthreads();
         }
     } else {
@@ -482,6 +497,13 @@ hipError_t launch_eval_persistent(const uint64_t *boards, size_t n, uint4 *out,
                                   const EvalScratch &S, int grid, const DevTables &T,
                                   hipStream_t s)
 {
+    return launch_eval_persistent_slots(boards, n, out, S, grid, grid, T, s);
+}
+
+hipError_t launch_eval_persistent_slots(const uint64_t *boards, size_t n, uint4 *out,
+                                        const EvalScratch &S, int grid, int slots,
+                                        const DevTables &T, hipStream_t s)
+{
     (void)n;
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -489,12 +511,14 @@ hipError_t launch_eval_persistent(const uint64_t *boards, size_t n, uint4 *out,
     if (e != hipSuccess) return e;
     const void *kern[3] = {(const void *)eval_persistent_kernel<0>, (const void *)eval_persistent_kernel<1>,
                            (const void *)eval_persistent_kernel<2>};
-    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, S.counter, 3);
+    if (slots < 1 || slots > grid) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, S.counter, 4);
     for (int c = 0; c < 3; c++) {
         const int lds = eval_class_lds_bytes(c);
         e = allow_lds(kern[c], lds);
         if (e != hipSuccess) return e;
-        // class 0 owns the global layer slots: one per workgroup of `grid`
+        // class 0: `grid` workgroups, the first `slots` of them owning a
+        // global layer slot each
         int g = grid;
         if (c > 0) {
             int per = 0;
@@ -504,11 +528,11 @@ hipError_t launch_eval_persistent(const uint64_t *boards, size_t n, uint4 *out,
         }
         switch (c) {
         case 0: hipLaunchKernelGGL(eval_persistent_kernel<0>, dim3(g), dim3(256), lds, s, boards, S.order,
-                                   S.start, S.counter, out, S.global_layers, T); break;
+                                   S.start, S.counter, out, S.global_layers, slots, T); break;
         case 1: hipLaunchKernelGGL(eval_persistent_kernel<1>, dim3(g), dim3(256), lds, s, boards, S.order,
-                                   S.start, S.counter, out, S.global_layers, T); break;
+                                   S.start, S.counter, out, S.global_layers, slots, T); break;
         default: hipLaunchKernelGGL(eval_persistent_kernel<2>, dim3(g), dim3(256), lds, s, boards, S.order,
-                                    S.start, S.counter, out, S.global_layers, T); break;
+                                    S.start, S.counter, out, S.global_layers, slots, T); break;
         }
     }
     return hipGetLastError();

@@ -12,6 +12,9 @@ namespace pg {
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *where);
 int device_tables(DevTables *out);
+// The current device's tables if device_tables() has uploaded them already
+// (0), else nonzero; never allocates.
+int device_tables_ready(DevTables *out);
 
 bool section_valid(const pentago_section &s);
 int section_mover(const pentago_section &s);

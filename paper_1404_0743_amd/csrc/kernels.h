@@ -111,6 +111,11 @@ hipError_t launch_eval_bin(const uint64_t *boards, size_t n, const EvalScratch &
 hipError_t launch_eval_persistent(const uint64_t *boards, size_t n, uint4 *out,
                                   const EvalScratch &S, int grid, const DevTables &T,
                                   hipStream_t s);
+// The same with only the first `slots` workgroups of class 0 owning a global
+// layer slot (1 <= slots <= grid; global_layers holds `slots` slots).
+hipError_t launch_eval_persistent_slots(const uint64_t *boards, size_t n, uint4 *out,
+                                        const EvalScratch &S, int grid, int slots,
+                                        const DevTables &T, hipStream_t s);
 hipError_t launch_eval_group(const uint64_t *boards, int e, int first, int count, uint4 *out,
                              const EvalScratch &S, const DevTables &T, hipStream_t s);
 

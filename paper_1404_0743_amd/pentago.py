@@ -85,6 +85,8 @@ _SIGS = {
     "pentago_eval_deep": ([Board, _P, _P], ctypes.c_int),
     "pentago_eval_deep_parity": ([Board, ctypes.c_int, _P, _P], ctypes.c_int),
     "pentago_eval_batch_grouped": ([_P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
+    "pentago_init": ([], ctypes.c_int),
+    "pentago_eval_batch_noalloc": ([_P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
     "pentago_serve_create": ([_P, _P], ctypes.c_int),
     "pentago_serve_add_section": ([_P, Section, _P], ctypes.c_int),
     "pentago_serve_submit": ([_P, Board, _P], ctypes.c_int),
@@ -368,6 +370,20 @@ def pentago_eval_batch(boards, out, status=None, stream=None, grouped=False):
     f = lib().pentago_eval_batch_grouped if grouped else lib().pentago_eval_batch
     _check(f(_dev_ptr(boards), n, _dev_ptr(out), _dev_ptr(status), _stream(stream)),
            "pentago_eval_batch" + ("_grouped" if grouped else ""))
+
+
+def pentago_init():
+    """Upload the tables and resolve the allocation-free call's scratch on the
+    current device."""
+    _check(lib().pentago_init(), "pentago_init")
+
+
+def pentago_eval_batch_noalloc(boards, out, status=None, stream=None):
+    """pentago_eval_batch with its scratch in the library's fixed device
+    array (no allocation); at most 2^20 boards; pentago_init() first."""
+    n = boards.numel() * boards.element_size() // 8
+    _check(lib().pentago_eval_batch_noalloc(_dev_ptr(boards), n, _dev_ptr(out), _dev_ptr(status),
+                                            _stream(stream)), "pentago_eval_batch_noalloc")
 
 
 # ---------------------------------------------------------------- serving
