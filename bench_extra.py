@@ -22,7 +22,9 @@
                  and 63 GB) over representatives: one batched launch, a
                  hipGraph replay, and one launch per section; then 2^15
                  positions of 34-35 stones answered by a server holding only
-                 those representatives.
+                 those representatives; then slice 33 (1,343 sections,
+                 337.8 GB) from the slice-34 representatives, streamed
+                 through a 64 GB arena in batches.
   deep           one position each of 22, 20 and 18 stones solved from scratch
                  (pentago_eval_deep: the DAG of 14, 16, 18 empty cells across
                  the GPU, layers in HBM).
@@ -392,6 +394,37 @@ def slices(P, torch, stream):
                 "p50_us": st["p50_us"], "p99_us": st["p99_us"],
                 "answers_equal_search": bool(np.array_equal(ref.cpu().numpy().view(np.uint64), got[:4096]))}
         above = tables
+    # slice 33 (1,343 sections, 337.8 GB of tables: more than the GPU holds
+    # next to slice 34) from the slice-34 representatives, streamed through
+    # one 64 GB arena in batches; the time counts the batched launches only
+    # (HIP events around each), not the per-batch checksums of the sink
+    evs = []
+    sums = []
+    w = torch.randint(-(1 << 62), 1 << 62, (8,), dtype=torch.int64, device="cuda")
+
+    def sink(tables):
+        sums.append(sum((t * w).sum() for t in tables.values()))
+
+    t0 = time.perf_counter()
+    nb = S.solve_slice_streamed(33, above, sink, stream=stream, events=evs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = sum(a.elapsed_time(b) for a, b in evs)
+    secs = P.pentago_slice_sections(33)
+    entries = sum(P.pentago_section_shape(s)[1] for s in secs)
+    reads = 0
+    for s in secs:
+        for j in range(4):
+            if sum(s[j]) < 9:
+                rep, _ = P.pentago_section_standardize(P.pentago_child_section(s, j))
+                reads += P.pentago_section_shape(rep)[1]
+    pos = S.slice_positions(33)
+    res["slice33_streamed"] = {
+        "sections": len(secs), "entries": entries, "bytes_written": 64 * entries, "batches": nb,
+        "arena_bytes": 64 << 30, "gpu_ms": gpu_ms, "wall_s": wall,
+        "positions": pos, "positions_per_s": pos / (gpu_ms * 1e-3),
+        "algorithmic_GB_s": 64 * (entries + reads) / (gpu_ms * 1e-3) / 1e9}
+    log("slice 33 streamed: %d batches, %.1f ms GPU, %.1f s wall" % (nb, gpu_ms, wall))
     del above
     torch.cuda.empty_cache()
     return res

@@ -242,6 +242,8 @@ int make_job(const pentago_section &s, const pentago_superinfo *const child[4],
     if (force_d >= 0 && ((J->emask >> force_d) & 1)) best = force_d;
     J->d = best >= 0 ? best : 3;
     J->e = J->d == 3 ? 2 : 3;
+    // every pattern of a (black, white) class has the same empty cells count
+    J->nchd = (J->emask >> J->d) & 1 ? 9 - s.black[J->d] - s.white[J->d] : 0;
     int o[2], n = 0;
     for (int j = 0; j < 4; j++)
         if (j != J->d && j != J->e) o[n++] = j;

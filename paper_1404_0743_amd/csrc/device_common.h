@@ -134,16 +134,32 @@ __device__ __forceinline__ uint4 quad_xor(uint4 a)
 }
 
 // One exchange stage: slot p of lane l takes slot p ^ X of lane l ^ X when
-// bit X of l differs from bit X of p.
+// bit X of l differs from bit X of p.  Written as keep ? own : moved, so that
+// each dword is one select whose moved operand is the DPP source.
+template <int X>
+__device__ __forceinline__ uint32_t quad_pick(bool keep, uint32_t own, uint32_t other)
+{
+    constexpr int ctrl = X == 1 ? 0xB1 : 0x4E;
+    // the exchange runs in every lane (a lane reads its partner's register),
+    // the select after it
+    const uint32_t moved = quad_perm<ctrl>(other);
+    return keep ? own : moved;
+}
+
 template <int X>
 __device__ __forceinline__ void quad_stage(uint4 (&r)[4], int l)
 {
+    const bool set = (l & X) != 0;
     uint4 t[4];
 #pragma unroll
-    for (int p = 0; p < 4; p++) t[p] = quad_xor<X>(r[p ^ X]);
+    for (int p = 0; p < 4; p++) {
+        const bool keep = set == ((p & X) != 0);
+        const uint4 o = r[p ^ X];
+        t[p] = make_uint4(quad_pick<X>(keep, r[p].x, o.x), quad_pick<X>(keep, r[p].y, o.y),
+                          quad_pick<X>(keep, r[p].z, o.z), quad_pick<X>(keep, r[p].w, o.w));
+    }
 #pragma unroll
-    for (int p = 0; p < 4; p++)
-        if ((l ^ p) & X) r[p] = t[p];
+    for (int p = 0; p < 4; p++) r[p] = t[p];
 }
 
 // After this, slot p of quad lane l holds piece l of quad lane p's entry.

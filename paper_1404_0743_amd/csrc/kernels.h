@@ -60,6 +60,7 @@ struct SweepJob {
     uint4 *out;
     int mover;         // 1 black, 2 white
     int d;             // dimension whose child lines are staged in LDS
+    int nchd;          // empty cells of quadrant d (children of every parent along d; 0: none)
     int emask;         // dimensions whose quadrant has empty cells
     int odmask;        // dimensions whose children are full boards evaluated on demand
     int e;             // dimension that groups G lines into a tile (3, or 2 when d == 3)
@@ -83,6 +84,8 @@ struct SweepJob {
 // Host launchers (sweep.hip, endgame.hip, symmetry.hip).
 hipError_t launch_sweep(const SweepJob &job, const DevTables &T, hipStream_t s);
 hipError_t launch_transform(const SymJob &job, const DevTables &T, hipStream_t s);
+// A section of full boards (no empty cell): one launch over half-blocks.
+hipError_t launch_terminal(const SweepJob &job, const DevTables &T, hipStream_t s);
 // Prepare the A/B child terms of dimension j (j in emask, j != d).
 hipError_t launch_prep(const SweepJob &job, int j, const DevTables &T, hipStream_t s);
 hipError_t launch_prep_batch(const SweepJob *dev_jobs, const int *dev_unit,

@@ -415,48 +415,128 @@ PG_HD uint32_t union_pairs2(uint32_t lo, uint32_t hi)
     return prod16(nib(lo, 0), nib(hi, 0)) | prod16(nib(lo, 1), nib(hi, 1));
 }
 
+// The five-set factors over pairs of quadrants.  Every group of lines above
+// depends on the patterns of two quadrants, and each three-quadrant line on
+// a product of two quadrants' sets with a third quadrant's; so the five-set
+// is assembled from six pair terms, each a function of two quadrants'
+// LineMasks only, already laid out as the 32-bit words of a Set256 (word
+// 2 g3 + p holds g2 = 2p in its low half and g2 = 2p + 1 in its high half,
+// g0 + 4 g1 inside a half).  A tile of entries sharing patterns can build the
+// pair terms once and assemble each entry from them.
+//   pair01 (Q0,Q1): {S01, P012, P013} each repeated in both halves, 0
+//   pair02 (Q0,Q2): E02 for p = 0, 1 (the left columns over g0, g2), and
+//                   B for p = 0, 1 (T023's Q0 set where T023's Q2 set holds g2)
+//   pair12 (Q1,Q2): E12 for p = 0, 1 (anti-diagonals over g1, g2), and
+//                   C for p = 0, 1 (T123's Q1 set where its Q2 set holds g2)
+//   pair03 (Q0,Q3): per g3, the long diagonals over g0 (both halves)
+//   pair13 (Q1,Q3): per g3, the right columns over g1 (both halves)
+//   pair23 (Q2,Q3): words 0-7: the bottom rows over g2, g3 as half-word masks;
+//                   8-9: the halves where T012's Q2 set holds g2; 10: T013's
+//                   Q3 set | T023's Q3 set << 4 | T123's Q3 set << 8; 11: 0
+PG_HD uint32_t halves(uint32_t lo, uint32_t hi) { return (lo & 0xffffu) | (hi << 16); }
+PG_HD uint32_t both_halves(uint32_t x) { return halves(x, x); }
+PG_HD uint32_t bit_halfmask(uint32_t set, int i) { return (((set >> i) & 1u) ? 0x0000ffffu : 0u) | (((set >> (i + 1)) & 1u) ? 0xffff0000u : 0u); }
+
+PG_HD uint4 pair01(const LineMasks &q0, const LineMasks &q1)
+{
+    const uint32_t S01 = union_pairs6(q0.a, q1.a);
+    const uint32_t P012 = prod16(nib(q0.c, 4), nib(q1.c, 4));
+    const uint32_t P013 = prod16(nib(q0.c, 2), nib(q1.c, 2));
+    return make_uint4(both_halves(S01), both_halves(P012), both_halves(P013), 0u);
+}
+
+PG_HD uint4 pair02(const LineMasks &q0, const LineMasks &q2)
+{
+    const uint32_t S02 = union_pairs6(q0.b, q2.b);  // g0 + 4 g2
+    const uint32_t b0 = rep_g0(nib(q0.c, 3)), b2 = nib(q2.c, 3);
+    uint32_t e[2], b[2];
+#pragma unroll
+    for (int p = 0; p < 2; p++) {
+        e[p] = halves(rep_g0(nib(S02, 2 * p)), rep_g0(nib(S02, 2 * p + 1)));
+        b[p] = halves(((b2 >> (2 * p)) & 1u) ? b0 : 0u, ((b2 >> (2 * p + 1)) & 1u) ? b0 : 0u);
+    }
+    return make_uint4(e[0], e[1], b[0], b[1]);
+}
+
+PG_HD uint4 pair12(const LineMasks &q1, const LineMasks &q2)
+{
+    const uint32_t S12 = union_pairs2(q1.c, q2.c);  // g1 + 4 g2
+    const uint32_t c1 = fill_g1(nib(q1.c, 5)), c2 = nib(q2.c, 5);
+    uint32_t e[2], c[2];
+#pragma unroll
+    for (int p = 0; p < 2; p++) {
+        e[p] = halves(fill_g1(nib(S12, 2 * p)), fill_g1(nib(S12, 2 * p + 1)));
+        c[p] = halves(((c2 >> (2 * p)) & 1u) ? c1 : 0u, ((c2 >> (2 * p + 1)) & 1u) ? c1 : 0u);
+    }
+    return make_uint4(e[0], e[1], c[0], c[1]);
+}
+
+PG_HD uint4 pair03(const LineMasks &q0, const LineMasks &q3)
+{
+    const uint32_t S03 = union_pairs2(q0.c, q3.c);  // g0 + 4 g3
+    return make_uint4(both_halves(rep_g0(nib(S03, 0))), both_halves(rep_g0(nib(S03, 1))),
+                      both_halves(rep_g0(nib(S03, 2))), both_halves(rep_g0(nib(S03, 3))));
+}
+
+PG_HD uint4 pair13(const LineMasks &q1, const LineMasks &q3)
+{
+    const uint32_t S13 = union_pairs6(q1.b, q3.b);  // g1 + 4 g3
+    return make_uint4(both_halves(fill_g1(nib(S13, 0))), both_halves(fill_g1(nib(S13, 1))),
+                      both_halves(fill_g1(nib(S13, 2))), both_halves(fill_g1(nib(S13, 3))));
+}
+
+PG_HD void pair23(const LineMasks &q2, const LineMasks &q3, uint4 out[3])
+{
+    const uint32_t S23 = union_pairs6(q2.a, q3.a);  // g2 + 4 g3
+    uint32_t w[12];
+#pragma unroll
+    for (int g3 = 0; g3 < 4; g3++)
+#pragma unroll
+        for (int p = 0; p < 2; p++) w[2 * g3 + p] = bit_halfmask(S23, 2 * p + 4 * g3);
+    const uint32_t a2 = nib(q2.c, 4);
+    w[8] = bit_halfmask(a2, 0);
+    w[9] = bit_halfmask(a2, 2);
+    w[10] = nib(q3.c, 2) | (nib(q3.c, 3) << 4) | (nib(q3.c, 5) << 8);
+    w[11] = 0;
+    out[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    out[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    out[2] = make_uint4(w[8], w[9], w[10], w[11]);
+}
+
+// all-ones when bit i of x is set, else 0
+PG_HD uint32_t bit_mask(uint32_t x, int i) { return ((x >> i) & 1u) ? 0xffffffffu : 0u; }
+
+PG_HD Set256 five_assemble(const uint4 &t01, const uint4 &t02, const uint4 &t12, const uint4 &t03,
+                           const uint4 &t13, const uint4 (&t23)[3])
+{
+    const uint32_t e02[2] = {t02.x, t02.y}, bw[2] = {t02.z, t02.w};
+    const uint32_t e12[2] = {t12.x, t12.y}, cw[2] = {t12.z, t12.w};
+    const uint32_t z03[4] = {t03.x, t03.y, t03.z, t03.w}, z13[4] = {t13.x, t13.y, t13.z, t13.w};
+    const uint32_t s23[8] = {t23[0].x, t23[0].y, t23[0].z, t23[0].w, t23[1].x, t23[1].y, t23[1].z, t23[1].w};
+    const uint32_t a2m[2] = {t23[2].x, t23[2].y}, nb = t23[2].z;
+    uint32_t Y[2], Z[4];
+#pragma unroll
+    for (int p = 0; p < 2; p++) Y[p] = e02[p] | e12[p] | t01.x | (t01.y & a2m[p]);
+#pragma unroll
+    for (int g3 = 0; g3 < 4; g3++) Z[g3] = z03[g3] | z13[g3] | (t01.z & bit_mask(nb, g3));
+    Set256 r;
+#pragma unroll
+    for (int g3 = 0; g3 < 4; g3++) {
+        const uint32_t bm = bit_mask(nb, 4 + g3), cm = bit_mask(nb, 8 + g3);
+#pragma unroll
+        for (int p = 0; p < 2; p++)
+            r.w[2 * g3 + p] = Y[p] | Z[g3] | s23[2 * g3 + p] | (bw[p] & bm) | (cw[p] & cm);
+    }
+    return r;
+}
+
 // The five-set of one colour from the line masks of its four quadrants.
 PG_HD Set256 five_set(const LineMasks &q0, const LineMasks &q1, const LineMasks &q2,
                       const LineMasks &q3)
 {
-    // two-quadrant groups, each as a 16-bit set over its two dimensions
-    const uint32_t S01 = union_pairs6(q0.a, q1.a);  // g0 + 4 g1
-    const uint32_t S23 = union_pairs6(q2.a, q3.a);  // g2 + 4 g3
-    const uint32_t S02 = union_pairs6(q0.b, q2.b);  // g0 + 4 g2
-    const uint32_t S13 = union_pairs6(q1.b, q3.b);  // g1 + 4 g3
-    const uint32_t S03 = union_pairs2(q0.c, q3.c);  // g0 + 4 g3
-    const uint32_t S12 = union_pairs2(q1.c, q2.c);  // g1 + 4 g2
-    // three-quadrant lines
-    const uint32_t P013 = prod16(nib(q0.c, 2), nib(q1.c, 2)), a3 = nib(q3.c, 2);
-    const uint32_t b0 = rep_g0(nib(q0.c, 3)), b2 = nib(q2.c, 3), b3 = nib(q3.c, 3);
-    const uint32_t P012 = prod16(nib(q0.c, 4), nib(q1.c, 4)), a2 = nib(q2.c, 4);
-    const uint32_t c1 = fill_g1(nib(q1.c, 5)), c2 = nib(q2.c, 5), c3 = nib(q3.c, 5);
-
-    uint32_t Y[4], Z[4];
-#pragma unroll
-    for (int t = 0; t < 4; t++) {
-        Y[t] = rep_g0(nib(S02, t)) | fill_g1(nib(S12, t)) | (((a2 >> t) & 1u) ? P012 : 0u) | S01;
-        Z[t] = rep_g0(nib(S03, t)) | fill_g1(nib(S13, t)) | (((a3 >> t) & 1u) ? P013 : 0u);
-    }
-    Set256 r;
-#pragma unroll
-    for (int g3 = 0; g3 < 4; g3++) {
-#pragma unroll
-        for (int p = 0; p < 2; p++) {
-            uint32_t half[2];
-#pragma unroll
-            for (int h = 0; h < 2; h++) {
-                const int g2 = 2 * p + h;
-                uint32_t v = Y[g2] | Z[g3];
-                v |= ((S23 >> (g2 + 4 * g3)) & 1u) ? 0xffffu : 0u;
-                v |= (((b2 >> g2) & (b3 >> g3)) & 1u) ? b0 : 0u;
-                v |= (((c2 >> g2) & (c3 >> g3)) & 1u) ? c1 : 0u;
-                half[h] = v;
-            }
-            r.w[2 * g3 + p] = half[0] | (half[1] << 16);
-        }
-    }
-    return r;
+    uint4 t23[3];
+    pair23(q2, q3, t23);
+    return five_assemble(pair01(q0, q1), pair02(q0, q2), pair12(q1, q2), pair03(q0, q3), pair13(q1, q3), t23);
 }
 
 // ------------------------------------------------------------------------

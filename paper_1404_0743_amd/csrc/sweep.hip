@@ -232,6 +232,19 @@ __device__ __forceinline__ void or_rotated(Set256 &acc, const uint32_t *p, int k
     }
 }
 
+// The same set, read instead of ORed (the first child of a parent).
+__device__ __forceinline__ Set256 load_rotated(const uint32_t *p, int k)
+{
+    Set256 r;
+#pragma unroll
+    for (int g3 = 0; g3 < 4; g3++) {
+        const uint2 v = *(const uint2 *)(p + 2 * ((g3 - k) & 3));
+        r.w[2 * g3] = v.x;
+        r.w[2 * g3 + 1] = v.y;
+    }
+    return r;
+}
+
 // Children of one parent along a dimension JD that is not staged: their
 // A/B terms were prepared per child entry by prep_kernel, in the parent's
 // internal layout (64 B each, in the child section's blocked order).
@@ -330,9 +343,12 @@ int sweep_lds_bytes(int G, int mD, int cmD)
 }
 
 // SYMC: the staged child is held as its representative (J.csym[D] != 0).
+// STAGED: quadrant D has empty cells (every section but full boards, which
+// the one-section sweep hands to the terminal kernel; only the batched forms
+// run full boards here).
 // Always inlined: the persistent kernels hold several instantiations, and a
 // call would spill the caller's registers to scratch.
-template <int D, bool SYMC = false>
+template <int D, bool SYMC = false, bool STAGED = true>
 __device__ __forceinline__ void sweep_tile(const SweepJob &J, const DevTables &T, long long tile, void *lds_base)
 {
     // tile = ((i_O1 * m_O2) + i_O2) * ngroups + group of G lines along E
@@ -351,7 +367,7 @@ __device__ __forceinline__ void sweep_tile(const SweepJob &J, const DevTables &T
     const int me = J.m[E];
     const int nlines = min(J.G, me - grp * J.G);
     const int c = J.mover;
-    const bool staged = (J.emask >> D) & 1;
+    constexpr bool staged = STAGED;
     const int cmD = J.cm[D];
     const int mD = J.m[D];
     const TileLds L = tile_lds(lds_base, J.G, mD, staged ? cmD : 0);
@@ -556,17 +572,25 @@ __device__ __forceinline__ void sweep_tile(const SweepJob &J, const DevTables &T
         Idx4 idx = base;
         idx.v[E] = base.v[E] + v;
         idx.v[D] = iD;
-        Set256 Wnt = s_zero(), Nnt = J.emask == 0 ? s_full() : s_zero();
+        Set256 Wnt, Nnt;
         if (staged) {
+            // quadrant D has J.nchd >= 1 empty cells in every pattern of its
+            // class: the first child starts the sums, a uniform loop adds the rest
             const PosChild &pr = L.pch[iD];
             const uint32_t *line = L.rec + kRecWords * v;
-            const int n = pr.nchild;
-            for (int e = 0; e < n; e++) {
+            const uint32_t c0 = pr.child[0];
+            const uint32_t *r0 = line + kRecWords * J.G * (c0 & 0xfff);
+            Wnt = load_rotated(r0, c0 >> 12);
+            Nnt = load_rotated(r0 + 8, c0 >> 12);
+            for (int e = 1; e < J.nchd; e++) {
                 const uint32_t cc = pr.child[e];
                 const uint32_t *r = line + kRecWords * J.G * (cc & 0xfff);
                 or_rotated(Wnt, r, cc >> 12);
                 or_rotated(Nnt, r + 8, cc >> 12);
             }
+        } else {
+            Wnt = s_zero();
+            Nnt = J.emask == 0 ? s_full() : s_zero();
         }
         // Children along the other dimensions with empty cells.
         if (J.emask & ~(1 << D)) {
@@ -644,7 +668,9 @@ __device__ __forceinline__ void sweep_batch_loop(const SweepJob *jobs, const lon
         const SweepJob &J = jobs[lo];
         const long long local = t - tile_start[lo];
         const bool symc = SYMS && J.csym[J.d] != 0 && ((J.emask >> J.d) & 1) && !((J.odmask >> J.d) & 1);
-        if (symc) {
+        if (J.emask == 0) {
+            sweep_tile<3, false, false>(J, T, local, (void *)lds);  // full boards
+        } else if (symc) {
             switch (J.d) {
             case 0: sweep_tile<0, SYMS>(J, T, local, (void *)lds); break;
             case 1: sweep_tile<1, SYMS>(J, T, local, (void *)lds); break;

@@ -46,7 +46,8 @@ int run_job(SweepJob &J, const DevTables &T, hipStream_t st)
         J.prep[j] = J.prep_out[j] = (uint4 *)prep[j];
         e = launch_prep(J, j, T, st);
     }
-    if (e == hipSuccess) e = launch_sweep(J, T, st);
+    // full boards (no empty cell) take the terminal kernel
+    if (e == hipSuccess) e = J.emask ? launch_sweep(J, T, st) : launch_terminal(J, T, st);
     for (int j = 0; j < 4; j++)
         if (prep[j]) (void)hipFreeAsync(prep[j], st);
     if (e != hipSuccess) return hip_fail(e, "sweep launch");

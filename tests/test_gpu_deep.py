@@ -4,11 +4,13 @@ over the GPU layer by layer).
 
 Parity: against the oracle's minimax search (O2) for roots with up to four
 empty cells, and against the batched endgame solver (itself pinned to O2) for
-1..10 empty cells.  Beyond that, properties that hold at any size: a root's
-table follows from the tables of its placements by the Section II recurrence
-(checked bit by bit at 12 empty cells, every placement solved separately),
-and tables are carried into each other by the board symmetries (14 empty
-cells).  The parity-halved form (32 B records) against minimax and against
+1..10 empty cells, and against stored minimax tables (O2, written by an
+oracle-only script) at 11, 12 and 13 empty cells.  Beyond that, properties
+that hold at any size: a root's table follows from the tables of its
+placements by the Section II recurrence (checked bit by bit at 12 empty
+cells, every placement solved separately), and tables are carried into each
+other by the board symmetries (14 empty cells, the map written out with
+numpy).  The parity-halved form (32 B records) against minimax and against
 the full-table solver up to 18 empty cells.  Full boards, boards showing
 fives, and argument errors."""
 import sys
@@ -113,17 +115,76 @@ def test_root_follows_from_its_placements_at_12_empty(P):
     assert np.array_equal(got, want)
 
 
+def d4_maps():
+    """The 8 board symmetries written out with numpy (independent of the
+    library and of the oracle): (cell permutation, quadrant map, sign), new
+    board = old[perm]; a reflection (sign -1) reverses every quadrant turn."""
+    out = []
+    base = np.arange(36).reshape(6, 6)
+    for refl in (False, True):
+        for k in range(4):
+            m = np.rot90(base, k)
+            if refl:
+                m = m[:, ::-1]
+            perm = m.reshape(36)
+            qmap = {}
+            for q in range(4):
+                cell = 6 * (3 * (q // 2) + 1) + (3 * (q % 2) + 1)  # quadrant centre
+                newpos = int(np.nonzero(perm == cell)[0][0])
+                qmap[q] = 2 * ((newpos // 6) // 3) + (newpos % 6) // 3
+            out.append((perm, qmap, -1 if refl else 1))
+    return out
+
+
 def test_symmetric_roots_at_14_empty(P):
+    """Values are invariant under the board symmetries (Section III): the
+    table of the image board at g' equals the root's at g, where g' moves
+    each quadrant's turns to its image quadrant, negated for a reflection."""
     root = I.random_play_boards(1, 22, 22, seed=75)[0]
-    base = deep(P, root)
-    for sym in (1, 4, 6):
-        img = np.zeros(36, np.uint8)
-        img[O.sym_cells(sym)] = root
-        log("symmetry", sym)
-        got = deep(P, img)
-        want = np.concatenate([P.pentago_debug_sym(base[:4], sym, [0, 0, 0, 0]),
-                               P.pentago_debug_sym(base[4:], sym, [0, 0, 0, 0])])
-        assert np.array_equal(got, want), sym
+    base = values(deep(P, root))
+    maps = d4_maps()
+    for k in (1, 2, 4, 6):
+        perm, qmap, sign = maps[k]
+        log("symmetry", k)
+        got = values(deep(P, root[perm]))
+        want = np.zeros(256, np.int8)
+        for g in range(256):
+            g2 = 0
+            for j in range(4):
+                g2 |= ((sign * ((g >> (2 * j)) & 3)) & 3) << (2 * qmap[j])
+            want[g2] = base[g]
+        assert np.array_equal(got, want), k
+
+
+def golden_deep():
+    """Boards with 11-13 empty cells and their minimax tables (oracle only:
+    tests/golden/make_deep_tables.py)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "deep_minimax.tab")
+    boards, tables = [], []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            cells, *words = line.split()
+            boards.append(np.array([int(c) for c in cells], np.uint8))
+            tables.append(np.array([int(w, 16) for w in words], np.uint64))
+    return np.array(boards), np.array(tables)
+
+
+def test_deep_roots_match_minimax_golden(P):
+    """Section VIII deep positions solved from scratch: 11, 12 and 13 empty
+    cells, every bit of the full table and of both parity halves against the
+    oracle's minimax tables."""
+    m = parity_masks()
+    boards, want = golden_deep()
+    assert len(boards) == 9
+    assert sorted(set(int((b == 0).sum()) for b in boards)) == [11, 12, 13]
+    for k, b in enumerate(boards):
+        log("deep vs golden minimax", k, "empties", int((b == 0).sum()))
+        assert np.array_equal(deep(P, b), want[k]), k
+        for par in (0, 1):
+            assert np.array_equal(deep_parity(P, b, par), want[k] & m[par]), (k, par)
 
 
 def test_full_boards_and_fives(P):

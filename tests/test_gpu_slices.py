@@ -152,3 +152,37 @@ def test_server_answers_whole_slices_from_representatives(P, slices):
     srv.close()
     assert st["lookups"] == len(boards) and st["searches"] == 0
     assert np.array_equal(got, O.minimax_tables(boards))
+
+
+def test_slice33_streamed_sampled_against_minimax(P, slices):
+    """Slice 33 (1,343 D4-minimal sections, 5.3e9 entries, 337.8 GB: more
+    than the GPU holds next to slice 34) solved whole from the slice-34
+    representatives in batches through one arena in HBM; after each batch,
+    every section is checked for win within not-lose and sampled, and the
+    samples are compared with the oracle's minimax search on the boards
+    (three empty cells)."""
+    S, _, t34 = slices
+    rng = np.random.default_rng(33)
+    boards, rows, seen = [], [], []
+    bad_subset = []
+
+    def sink(tables):
+        for counts, t in tables.items():
+            seen.append(counts)
+            if bool((t[:, :4] & ~t[:, 4:]).any()):
+                bad_subset.append(counts)
+            shape = O.section_shape(counts)
+            idxs = [[int(rng.integers(0, m)) for m in shape] for _ in range(2)]
+            offs = torch.tensor([O.section_offset(counts, i) for i in idxs], dtype=torch.int64, device="cuda")
+            boards.extend(O.section_board(counts, i) for i in idxs)
+            rows.append(from_dev(t.index_select(0, offs)))
+        log("slice 33: %d sections so far" % len(seen))
+
+    nb = S.solve_slice_streamed(33, t34, sink)
+    torch.cuda.synchronize()
+    assert nb > 1
+    assert len(seen) == 1343 and len(set(seen)) == 1343
+    assert set(seen) == set(P.pentago_slice_sections(33))
+    assert not bad_subset
+    log("slice 33: minimax on %d sampled entries" % len(boards))
+    assert np.array_equal(np.concatenate(rows), O.minimax_tables(np.array(boards)))
