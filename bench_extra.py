@@ -88,6 +88,10 @@ def endgame(P, torch, stream, boards, grouped_too):
     empt = (boards == 0).sum(axis=1)
     nodes = int(sum(NODES[e] for e in empt))
     res = {"roots": len(boards), "dag_nodes": nodes}
+    if grouped_too:
+        # the persistent form's workgroup sizes, tuned on these roots (set-up)
+        threads, _ = P.pentago_autotune_eval(codes, out, stream)
+        res["persistent_class_threads"] = list(threads)
     med, mn = _time(torch, stream, lambda: P.pentago_eval_batch(codes, out, status, stream), 5)
     res.update(persistent_ms=med, persistent_roots_per_s=len(boards) / (med * 1e-3),
                persistent_node_evals_per_s=nodes * 256 / (med * 1e-3))

@@ -261,6 +261,14 @@ int pentago_plan_destroy(pentago_sweep_plan *plan);
 int pentago_eval_batch(const pentago_board *boards, size_t n, pentago_superinfo *out,
                        int32_t *status, void *hip_stream);
 
+/* The endgame autotuner: times pentago_eval_batch on these boards with 256
+ * and 512 threads per root for the workgroup-per-root classes (8-10 and 7
+ * empty cells) and keeps the fastest pair for later calls (process-wide).
+ * Leaves out holding the result; synchronises the stream.  threads (2 ints)
+ * and best_ms may be NULL.  Errors as pentago_eval_batch. */
+int pentago_autotune_eval(const pentago_board *boards, size_t n, pentago_superinfo *out, void *hip_stream,
+                          int threads[2], float *best_ms);
+
 /* The plain form of pentago_eval_batch: one launch per group of boards with
  * the same number of empty cells, one workgroup per board.  Same results.
  * Synchronises the stream once, to read the group sizes. */

@@ -69,8 +69,8 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Solve one root with a group of GROUP threads: the whole workgroup (256) or
-// one wave (64).  `buf0` and `buf1` hold two layers of A/B records (64 B per
+// Solve one root with a group of GROUP threads: the whole workgroup (256 or
+// 512) or one wave (64).  `buf0` and `buf1` hold two layers of A/B records (64 B per
 // node); `ftab` the five-set tables of the current layer; slot_q/slot_l (10
 // ints each, LDS) the root's empty cells.
 //
@@ -84,7 +84,7 @@ template <int GROUP>
 __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, uint4 *buf1,
                            uint4 *ftab, uint4 *out, int *s_slot_q, int *s_slot_l)
 {
-    const int lane = GROUP == 256 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+    const int lane = GROUP >= 256 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
     if (lane == 0) {
         int n = 0;
         for (int j = 0; j < 4; j++) {
@@ -97,7 +97,7 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
                 }
         }
     }
-    if (GROUP == 256) __syncthreads();
+    if (GROUP >= 256) __syncthreads();
     else wave_sync();
     const int e = R.e;
     const uint32_t *nodes = T.dag_node + T.dag_node_off[e];
@@ -143,7 +143,7 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
             dst[0] = make_uint4(F.w[0], F.w[1], F.w[2], F.w[3]);
             dst[1] = make_uint4(F.w[4], F.w[5], F.w[6], F.w[7]);
         }
-        if (GROUP == 256) __syncthreads();
+        if (GROUP >= 256) __syncthreads();
         else wave_sync();
         for (int i = n0 + lane; i < n1; i += GROUP) {
             const uint32_t nd = nodes[i];
@@ -184,7 +184,7 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
                 p[3] = make_uint4(B.w[4], B.w[5], B.w[6], B.w[7]);
             }
         }
-        if (GROUP == 256) __syncthreads();
+        if (GROUP >= 256) __syncthreads();
         else wave_sync();
         uint4 *tmp = cur;
         cur = prev;
@@ -272,8 +272,8 @@ constexpr int kWaveMaxEmpties = 6;
 // two layers of the widest 6-empty layer, then the five-set tables (C(6,3) = 20)
 constexpr int kWaveLdsBytes = 2 * 90 * 64 + 2 * 20 * 32;
 
-template <int CLS>
-__global__ void __launch_bounds__(256)
+template <int CLS, int NT>
+__global__ void __launch_bounds__(NT)
     eval_persistent_kernel(const uint64_t *boards, const int *order, const int *start,
                            unsigned long long *counter, uint4 *out, uint4 *gl, int slots, DevTables T)
 {
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(256)
                 if (item >= big) break;
                 const int root = order[item];
                 const RootInfo R = decode_root(boards[root]);
-                solve_root<256>(R, T, mine, mine + 4 * kDagGlobalLayer, lds, out + 4 * (size_t)root,
+                solve_root<NT>(R, T, mine, mine + 4 * kDagGlobalLayer, lds, out + 4 * (size_t)root,
                                 s_slots[0][0], s_slots[0][1]);
                 __syncthreads();
             }
@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(256)
             if (item >= hi) break;
             const int root = order[item];
             const RootInfo R = decode_root(boards[root]);
-            solve_root<256>(R, T, lds, lds + 4 * T.dag_max[R.e], lds + 8 * T.dag_max[R.e],
+            solve_root<NT>(R, T, lds, lds + 4 * T.dag_max[R.e], lds + 8 * T.dag_max[R.e],
                             out + 4 * (size_t)root, s_slots[0][0], s_slots[0][1]);
             __syncthreads();
         }
@@ -500,6 +500,44 @@ hipError_t launch_eval_persistent(const uint64_t *boards, size_t n, uint4 *out,
     return launch_eval_persistent_slots(boards, n, out, S, grid, grid, T, s);
 }
 
+// Workgroup size of the persistent classes 0 and 1 (256 or 512 threads per
+// root; class 2 takes a wave per root in 256-thread workgroups).
+static int g_class_threads[2] = {512, 256};
+
+void set_eval_class_threads(int c0, int c1)
+{
+    g_class_threads[0] = c0;
+    g_class_threads[1] = c1;
+}
+
+void get_eval_class_threads(int *c0, int *c1)
+{
+    *c0 = g_class_threads[0];
+    *c1 = g_class_threads[1];
+}
+
+template <int CLS, int NT>
+static hipError_t launch_class(int g, int lds, hipStream_t s, const uint64_t *boards, const EvalScratch &S,
+                               uint4 *out, int slots, const DevTables &T)
+{
+    const hipError_t e = allow_lds((const void *)eval_persistent_kernel<CLS, NT>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((eval_persistent_kernel<CLS, NT>), dim3(g), dim3(NT), lds, s, boards, S.order, S.start,
+                       S.counter, out, S.global_layers, slots, T);
+    return hipGetLastError();
+}
+
+template <int CLS, int NT>
+static int class_blocks_per_cu(int lds)
+{
+    int per = 0;
+    (void)allow_lds((const void *)eval_persistent_kernel<CLS, NT>, lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)eval_persistent_kernel<CLS, NT>, NT,
+                                                     lds) != hipSuccess)
+        return 1;
+    return std::max(1, per);
+}
+
 hipError_t launch_eval_persistent_slots(const uint64_t *boards, size_t n, uint4 *out,
                                         const EvalScratch &S, int grid, int slots,
                                         const DevTables &T, hipStream_t s)
@@ -509,33 +547,20 @@ hipError_t launch_eval_persistent_slots(const uint64_t *boards, size_t n, uint4 
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    const void *kern[3] = {(const void *)eval_persistent_kernel<0>, (const void *)eval_persistent_kernel<1>,
-                           (const void *)eval_persistent_kernel<2>};
     if (slots < 1 || slots > grid) return hipErrorInvalidValue;
     hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, S.counter, 4);
-    for (int c = 0; c < 3; c++) {
-        const int lds = eval_class_lds_bytes(c);
-        e = allow_lds(kern[c], lds);
-        if (e != hipSuccess) return e;
-        // class 0: `grid` workgroups, the first `slots` of them owning a
-        // global layer slot each
-        int g = grid;
-        if (c > 0) {
-            int per = 0;
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern[c], 256, lds);
-            if (e != hipSuccess) return e;
-            g = std::max(1, per) * cus;
-        }
-        switch (c) {
-        case 0: hipLaunchKernelGGL(eval_persistent_kernel<0>, dim3(g), dim3(256), lds, s, boards, S.order,
-                                   S.start, S.counter, out, S.global_layers, slots, T); break;
-        case 1: hipLaunchKernelGGL(eval_persistent_kernel<1>, dim3(g), dim3(256), lds, s, boards, S.order,
-                                   S.start, S.counter, out, S.global_layers, slots, T); break;
-        default: hipLaunchKernelGGL(eval_persistent_kernel<2>, dim3(g), dim3(256), lds, s, boards, S.order,
-                                    S.start, S.counter, out, S.global_layers, slots, T); break;
-        }
-    }
-    return hipGetLastError();
+    // class 0: `grid` workgroups (two per CU: the LDS of an 8-empty root),
+    // the first `slots` of them owning a global layer slot each
+    const int lds0 = eval_class_lds_bytes(0), lds1 = eval_class_lds_bytes(1), lds2 = eval_class_lds_bytes(2);
+    e = g_class_threads[0] == 512 ? launch_class<0, 512>(grid, lds0, s, boards, S, out, slots, T)
+                                  : launch_class<0, 256>(grid, lds0, s, boards, S, out, slots, T);
+    if (e != hipSuccess) return e;
+    if (g_class_threads[1] == 512)
+        e = launch_class<1, 512>(class_blocks_per_cu<1, 512>(lds1) * cus, lds1, s, boards, S, out, slots, T);
+    else
+        e = launch_class<1, 256>(class_blocks_per_cu<1, 256>(lds1) * cus, lds1, s, boards, S, out, slots, T);
+    if (e != hipSuccess) return e;
+    return launch_class<2, 256>(class_blocks_per_cu<2, 256>(lds2) * cus, lds2, s, boards, S, out, slots, T);
 }
 
 hipError_t launch_eval_direct(const uint64_t *boards, int n, uint4 *out, int cls,

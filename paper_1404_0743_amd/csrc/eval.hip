@@ -153,6 +153,51 @@ int pentago_eval_batch(const pentago_board *boards, size_t n, pentago_superinfo 
     return 0;
 }
 
+int pentago_autotune_eval(const pentago_board *boards, size_t n, pentago_superinfo *out, void *hip_stream,
+                          int threads[2], float *best_ms)
+{
+    if (n && (!boards || !out)) return fail(PENTAGO_EINVAL, "NULL boards or out");
+    if (n > (size_t)1 << 30) return fail(PENTAGO_ERANGE, "more than 2^30 boards");
+    if (n == 0) return 0;
+    const hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return fail(PENTAGO_EDEVICE, "hipEventCreate");
+    int best0 = 0, best1 = 0, rc = 0;
+    float best = 1e30f;
+    for (int c0 = 256; c0 <= 512 && rc == 0; c0 *= 2)
+        for (int c1 = 256; c1 <= 512 && rc == 0; c1 *= 2) {
+            set_eval_class_threads(c0, c1);
+            rc = pentago_eval_batch(boards, n, out, nullptr, hip_stream);  // warm-up
+            float t = 1e30f;
+            for (int rep = 0; rep < 3 && rc == 0; rep++) {
+                (void)hipEventRecord(a, st);
+                rc = pentago_eval_batch(boards, n, out, nullptr, hip_stream);
+                (void)hipEventRecord(b, st);
+                if (hipEventSynchronize(b) != hipSuccess) rc = fail(PENTAGO_EDEVICE, "hipEventSynchronize");
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, a, b);
+                t = std::min(t, ms);
+            }
+            if (rc == 0 && t < best) {
+                best = t;
+                best0 = c0;
+                best1 = c1;
+            }
+        }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return rc;
+    set_eval_class_threads(best0, best1);
+    rc = pentago_eval_batch(boards, n, out, nullptr, hip_stream);
+    if (threads) {
+        threads[0] = best0;
+        threads[1] = best1;
+    }
+    if (best_ms) *best_ms = best;
+    return rc;
+}
+
 int pentago_eval_batch_grouped(const pentago_board *boards, size_t n, pentago_superinfo *out,
                                int32_t *status, void *hip_stream)
 {

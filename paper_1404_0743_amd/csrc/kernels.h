@@ -119,6 +119,10 @@ hipError_t launch_eval_persistent(const uint64_t *boards, size_t n, uint4 *out,
 hipError_t launch_eval_persistent_slots(const uint64_t *boards, size_t n, uint4 *out,
                                         const EvalScratch &S, int grid, int slots,
                                         const DevTables &T, hipStream_t s);
+// Workgroup sizes of persistent endgame classes 0 and 1 (256 or 512), set
+// by the endgame autotuner; process-wide.
+void set_eval_class_threads(int c0, int c1);
+void get_eval_class_threads(int *c0, int *c1);
 hipError_t launch_eval_group(const uint64_t *boards, int e, int first, int count, uint4 *out,
                              const EvalScratch &S, const DevTables &T, hipStream_t s);
 

@@ -86,6 +86,7 @@ _SIGS = {
     "pentago_eval_deep_parity": ([Board, ctypes.c_int, _P, _P], ctypes.c_int),
     "pentago_eval_batch_grouped": ([_P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
     "pentago_init": ([], ctypes.c_int),
+    "pentago_autotune_eval": ([_P, ctypes.c_size_t, _P, _P, _P, _P], ctypes.c_int),
     "pentago_eval_batch_noalloc": ([_P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
     "pentago_serve_create": ([_P, _P], ctypes.c_int),
     "pentago_serve_add_section": ([_P, Section, _P], ctypes.c_int),
@@ -370,6 +371,17 @@ def pentago_eval_batch(boards, out, status=None, stream=None, grouped=False):
     f = lib().pentago_eval_batch_grouped if grouped else lib().pentago_eval_batch
     _check(f(_dev_ptr(boards), n, _dev_ptr(out), _dev_ptr(status), _stream(stream)),
            "pentago_eval_batch" + ("_grouped" if grouped else ""))
+
+
+def pentago_autotune_eval(boards, out, stream=None):
+    """Time the endgame classes' workgroup sizes on these boards, keep the
+    fastest; returns ((threads of class 0, of class 1), best ms)."""
+    n = boards.numel() * boards.element_size() // 8
+    th = (ctypes.c_int * 2)()
+    ms = ctypes.c_float()
+    _check(lib().pentago_autotune_eval(_dev_ptr(boards), n, _dev_ptr(out), _stream(stream), th,
+                                       ctypes.byref(ms)), "pentago_autotune_eval")
+    return (th[0], th[1]), ms.value
 
 
 def pentago_init():

@@ -98,3 +98,19 @@ def test_invalid_boards_are_counted(P):
     assert nbad == 6
     assert not got[5:].any()
     assert np.array_equal(got[:5], O.minimax_tables(good))
+
+
+def test_autotuned_class_threads_same_results(P):
+    """The endgame autotuner picks workgroup sizes for the per-root classes;
+    every pick leaves results bit-identical (8-10 empty cells included)."""
+    log("endgame autotune")
+    boards = np.concatenate([I.random_play_boards(500, 26, 33, seed=51)])
+    want, _ = gpu_eval(P, boards)
+    codes = torch.from_numpy(P.boards_to_codes(boards).view(np.int16).copy()).cuda()
+    out = torch.empty((len(boards), 8), dtype=torch.int64, device="cuda")
+    threads, ms = P.pentago_autotune_eval(codes, out)
+    torch.cuda.synchronize()
+    assert all(t in (256, 512) for t in threads) and ms > 0
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), want)
+    got, _ = gpu_eval(P, boards)
+    assert np.array_equal(got, want)
