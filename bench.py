@@ -118,6 +118,28 @@ def _blob_sha(path):
     return hashlib.sha1(b"blob %d\0" % len(data) + data).hexdigest()
 
 
+VALU_PEAK = 256 * 4 * 2.4e9 / 4   # wave64 VALU instructions/s: 256 CUs x 4 SIMD16 at 2.4 GHz
+
+
+def profile_counts(name):
+    """A committed rocprofv3 counter summary (profiles/<name>.json), or None
+    when any source it was taken on has changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    h = hashlib.sha1()
+    for src in d.get("sources", []):
+        full = os.path.join(ROOT, src)
+        if not os.path.exists(full):
+            return None
+        with open(full, "rb") as f:
+            h.update(f.read())
+    return d if h.hexdigest() == d.get("sources_sha1") else None
+
+
 def measured_traffic():
     """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, scaled by the copy-kernel calibration it records;
@@ -131,6 +153,20 @@ def measured_traffic():
     if not os.path.exists(src) or _blob_sha(src) != t.get("kernel_source_blob"):
         return None
     return t.get("bytes_per_launch")
+
+
+def roofline_valu(avg_ms):
+    """The sweep's VALU issue rate against the chip's: wave64 VALU
+    instructions per launch (committed counters, while the kernel sources
+    are unchanged) over the live mean launch time."""
+    d = profile_counts("sweep_kernel_section_36to35_valu")
+    if d is None:
+        return None
+    achieved = d["valu_instr"] / (avg_ms * 1e-3)
+    return {"bound": "alu", "achieved": achieved / 1e9, "peak": VALU_PEAK / 1e9,
+            "unit": "G wave64 VALU instructions/s", "frac": achieved / VALU_PEAK,
+            "instructions_per_launch": d["valu_instr"],
+            "source": "profiles/sweep_kernel_section_36to35_valu.json"}
 
 
 def main():
@@ -256,6 +292,7 @@ def main():
                    "tile_lines": tile["lines"], "tile_threads": tile["threads"], "tile_order": tile["order"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "roofline_valu": roofline_valu(avg_ms),
         "kernel_ms": {"sweep_avg": avg_ms, "sweep_min": float(np.min(kernel_ms)),
                       "sweep_median_single": float(np.median(kernel_ms)),
                       "terminal_child_section": terminal_ms},

@@ -62,6 +62,11 @@ def _parity_mask(p):
 PARITY0 = _parity_mask(0)
 
 
+def bench_profile(name):
+    import bench
+    return bench.profile_counts(name)
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -101,6 +106,17 @@ def endgame(P, torch, stream, boards, grouped_too):
         res.update(grouped_ms=med2, grouped_roots_per_s=len(boards) / (med2 * 1e-3),
                    persistent_over_grouped=med2 / med, same_bytes=bool(torch.equal(ref, out)))
     res["invalid_boards"] = int(status.item())
+    if grouped_too:
+        # VALU issue of the persistent form: the class kernels' instructions
+        # (committed counters, while their sources are unchanged) over its time
+        import bench
+        per = [bench.profile_counts("eval_persistent_kernel_class%d_2p20_roots_valu" % c) for c in range(3)]
+        if all(p is not None for p in per):
+            instr = sum(p["valu_instr"] for p in per)
+            res["roofline_valu"] = {"bound": "alu", "achieved": instr / (med * 1e-3) / 1e9,
+                                    "peak": bench.VALU_PEAK / 1e9, "unit": "G wave64 VALU instructions/s",
+                                    "frac": instr / (med * 1e-3) / bench.VALU_PEAK,
+                                    "per_class_frac": [p["valu_issue_frac"] for p in per]}
     return res
 
 
@@ -464,7 +480,11 @@ def deep(P, torch, stream):
         fw = out.cpu().numpy().view(np.uint64)
         # floor bytes: every node's record written once and read once
         floor = 2 * 64 * sum(nodes)
+        prof = bench_profile("deep_node_kernel_valu")
         res["empty%d" % e] = {"stones": stones, "dag_nodes": sum(nodes), "ms": med, "min_ms": mn,
+                              "valu_issue_frac_profiled": None if prof is None else
+                              {"full": prof["deep_node_kernel<false>"]["valu_issue_frac"],
+                               "parity_half": prof["deep_node_kernel<true>"]["valu_issue_frac"]},
                               "nodes_per_s": sum(nodes) / (med * 1e-3),
                               # 64 B per (node, child) edge read + 64 B per node
                               # written: L2 serves part of the edge reads, so
