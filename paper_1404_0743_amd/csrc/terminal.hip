@@ -6,12 +6,17 @@
 // The five-set factors into six pair terms, each a function of the patterns
 // of two quadrants (five_assemble in set256.h).  A first small kernel builds
 // every pair term of the section (for full boards each quadrant class has at
-// most 34 patterns, so all of them take under 300 KB); the entry kernel then
+// most 34 patterns, so all of them take under 300 KB; they are kept per
+// section geometry, see launch_terminal); the entry kernel then
 // takes one quarter of an 8^4 block per workgroup (Section IV layout: the
 // entries with block-local index i0 in [2q, 2q + 2), a contiguous range of the
 // table), copies the pair terms its patterns use into LDS and assembles each
 // entry's two five-sets from 12 table reads.
 #include "device_common.h"
+
+#include <array>
+#include <map>
+#include <mutex>
 
 namespace pg {
 
@@ -172,34 +177,99 @@ __global__ void __launch_bounds__(NT) terminal_kernel(SweepJob J, TermPairs Q)
     }
 }
 
+// Pair terms depend only on the section's four (black, white) classes and
+// the side to move, so they are built once per device and geometry and kept: the first call builds them on its stream and
+// records an event that later calls on other streams wait for.  At most
+// kPairCacheMax geometries are kept; beyond that a call builds its own in
+// stream-ordered scratch.
+constexpr int kPairCacheMax = 64;
+
+struct PairEntry {
+    void *buf;
+    hipEvent_t ready;
+};
+
+static std::mutex g_pair_mutex;
+static std::map<std::array<int, 10>, PairEntry> g_pairs;
+
+static TermPairs pair_layout(const SweepJob &J, void *buf)
+{
+    const size_t m0 = J.m[0], m1 = J.m[1], m2 = J.m[2], m3 = J.m[3];
+    TermPairs Q;
+    Q.t01 = (uint4 *)buf;
+    Q.t02 = Q.t01 + 2 * m0 * m1;
+    Q.t03 = Q.t02 + 2 * m0 * m2;
+    Q.t12 = Q.t03 + 2 * m0 * m3;
+    Q.t13 = Q.t12 + 2 * m1 * m2;
+    Q.t23 = Q.t13 + 2 * m1 * m3;
+    for (int j = 0; j < 4; j++) Q.m[j] = J.m[j];
+    return Q;
+}
+
+static size_t pair_bytes(const SweepJob &J)
+{
+    const size_t m0 = J.m[0], m1 = J.m[1], m2 = J.m[2], m3 = J.m[3];
+    return 2 * (m0 * m1 + m0 * m2 + m0 * m3 + m1 * m2 + m1 * m3 + 3 * m2 * m3) * sizeof(uint4);
+}
+
+static void launch_pairs(const SweepJob &J, const DevTables &T, const TermPairs &Q, hipStream_t s)
+{
+    const size_t m0 = J.m[0], m1 = J.m[1], m2 = J.m[2], m3 = J.m[3];
+    const size_t items = 2 * (m0 * m1 + m0 * m2 + m0 * m3 + m1 * m2 + m1 * m3 + m2 * m3);
+    hipLaunchKernelGGL(terminal_pairs_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, J, T, Q);
+}
+
 hipError_t launch_terminal(const SweepJob &J, const DevTables &T, hipStream_t s)
 {
     int nb = 1;
     for (int j = 0; j < 4; j++) nb *= (J.m[j] + 7) / 8;
     if (nb == 0) return hipSuccess;
-    const size_t m0 = J.m[0], m1 = J.m[1], m2 = J.m[2], m3 = J.m[3];
-    const size_t n01 = m0 * m1, n02 = m0 * m2, n03 = m0 * m3, n12 = m1 * m2, n13 = m1 * m3, n23 = m2 * m3;
-    const size_t slots = 2 * (n01 + n02 + n03 + n12 + n13 + 3 * n23);
-    void *buf = nullptr;
-    hipError_t e = hipMallocAsync(&buf, slots * sizeof(uint4), s);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
+    std::array<int, 10> key{dev};
+    for (int j = 0; j < 4; j++) {
+        key[1 + j] = J.qb[j];
+        key[5 + j] = J.m[j];
+    }
+    key[9] = J.mover;
+    void *own = nullptr;
     TermPairs Q;
-    Q.t01 = (uint4 *)buf;
-    Q.t02 = Q.t01 + 2 * n01;
-    Q.t03 = Q.t02 + 2 * n02;
-    Q.t12 = Q.t03 + 2 * n03;
-    Q.t13 = Q.t12 + 2 * n12;
-    Q.t23 = Q.t13 + 2 * n13;
-    for (int j = 0; j < 4; j++) Q.m[j] = J.m[j];
-    const size_t items = 2 * (n01 + n02 + n03 + n12 + n13 + n23);
-    hipLaunchKernelGGL(terminal_pairs_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, J, T, Q);
+    {
+        std::lock_guard<std::mutex> lock(g_pair_mutex);
+        auto it = g_pairs.find(key);
+        if (it != g_pairs.end()) {
+            Q = pair_layout(J, it->second.buf);
+            e = hipStreamWaitEvent(s, it->second.ready, 0);
+            if (e != hipSuccess) return e;
+        } else if ((int)g_pairs.size() < kPairCacheMax) {
+            PairEntry P{nullptr, nullptr};
+            e = hipMalloc(&P.buf, pair_bytes(J));
+            if (e != hipSuccess) return e;
+            e = hipEventCreateWithFlags(&P.ready, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                (void)hipFree(P.buf);
+                return e;
+            }
+            Q = pair_layout(J, P.buf);
+            launch_pairs(J, T, Q, s);
+            e = hipEventRecord(P.ready, s);
+            if (e != hipSuccess) return e;
+            g_pairs[key] = P;
+        } else {
+            e = hipMallocAsync(&own, pair_bytes(J), s);
+            if (e != hipSuccess) return e;
+            Q = pair_layout(J, own);
+            launch_pairs(J, T, Q, s);
+        }
+    }
     const unsigned tiles = (unsigned)(4 * nb);
     if (J.threads == 512)
         hipLaunchKernelGGL(terminal_kernel<512>, dim3(tiles), dim3(512), 0, s, J, Q);
     else
         hipLaunchKernelGGL(terminal_kernel<256>, dim3(tiles), dim3(256), 0, s, J, Q);
     e = hipGetLastError();
-    (void)hipFreeAsync(buf, s);
+    if (own) (void)hipFreeAsync(own, s);
     return e;
 }
 
