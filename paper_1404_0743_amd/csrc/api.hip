@@ -51,7 +51,7 @@ int device_tables(DevTables *out)
     DevTables T;
     memset(&T, 0, sizeof(T));
     std::vector<uint32_t> nodes;
-    std::vector<uint16_t> ranks, submask, subrank;
+    std::vector<uint16_t> ranks, submask, subrank, edges;
     for (int k = 0; k <= 10; k++) {
         const DagLayout &L = dag_layout(k);
         T.dag_node_off[k] = (int)nodes.size();
@@ -61,6 +61,7 @@ int device_tables(DevTables *out)
         ranks.insert(ranks.end(), L.rank.begin(), L.rank.end());
         submask.insert(submask.end(), L.sub_mask.begin(), L.sub_mask.end());
         subrank.insert(subrank.end(), L.sub_rank.begin(), L.sub_rank.end());
+        edges.insert(edges.end(), L.edge.begin(), L.edge.end());
         for (int t = 0; t < 12; t++) {
             T.dag_layer[k][t] = t <= k + 1 ? L.layer_start[t] : 0;
             T.dag_sub_start[k][t] = t <= k + 1 ? L.sub_start[t] : 0;
@@ -74,7 +75,7 @@ int device_tables(DevTables *out)
         size_t bytes;
         void **dst;
     };
-    void *canon, *qinfo, *lm, *dn, *dr, *sel, *cref, *uref, *smask, *srank, *symmap, *symcode;
+    void *canon, *qinfo, *lm, *dn, *dr, *sel, *cref, *uref, *smask, *srank, *symmap, *symcode, *dedge;
     Up ups[] = {{H.canon.data(), H.canon.size() * 2, &canon},
                 {H.qinfo.data(), H.qinfo.size() * sizeof(QInfo), &qinfo},
                 {H.lm.data(), H.lm.size() * sizeof(LineMasks), &lm},
@@ -86,7 +87,8 @@ int device_tables(DevTables *out)
                 {submask.data(), submask.size() * 2, &smask},
                 {subrank.data(), subrank.size() * 2, &srank},
                 {H.symmap.data(), H.symmap.size() * 2, &symmap},
-                {H.symcode.data(), H.symcode.size() * 2, &symcode}};
+                {H.symcode.data(), H.symcode.size() * 2, &symcode},
+                {edges.data(), edges.size() * 2, &dedge}};
     for (Up &u : ups) {
         e = hipMalloc(&p, u.bytes);
         if (e != hipSuccess) return hip_fail(e, "hipMalloc(tables)");
@@ -99,6 +101,7 @@ int device_tables(DevTables *out)
     T.lm = (const LineMasks *)lm;
     T.dag_node = (const uint32_t *)dn;
     T.dag_rank = (const uint16_t *)dr;
+    T.dag_edge = (const uint4 *)dedge;
     T.sel = (const uint4 *)sel;
     T.chunk_ref = (const uint16_t *)cref;
     T.u_ref = (const uint32_t *)uref;

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -18,6 +19,11 @@ struct pentago_sweep_plan {
     int njobs = 0, nunits = 0;
     long long total_tiles = 0, total_chunks = 0;
     int lds_bytes = 0, grid = 0;
+    // jobs [0, nbig) have tiles above kBatchLds of LDS even with one line;
+    // they take a second persistent launch, beside the first on a side stream
+    int nbig = 0;
+    long long tiles_big = 0;
+    int lds_big = 0, grid_big = 0;
     char *dev = nullptr;  // one device block: jobs, tile starts, units, chunk starts, counter, prep
     SweepJob *d_jobs = nullptr;
     long long *d_tile_start = nullptr;
@@ -54,6 +60,19 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
             return fail(PENTAGO_EINVAL, "jobs of one call must share the stone count");
         int rc = make_job(jobs[i].section, jobs[i].child, jobs[i].out, &J[i], -1, 0);
         if (rc) return rc;
+        // in a batch, stage the quadrant with the longest lines (the most
+        // patterns; ties: the larger child class): short lines pay the
+        // per-line table set-up over few parents, and the children of the
+        // other quadrants go through the one batched prep launch anyway
+        int dl = -1;
+        for (int j = 0; j < 4; j++)
+            if (((J[i].emask >> j) & 1) &&
+                (dl < 0 || J[i].m[j] > J[i].m[dl] || (J[i].m[j] == J[i].m[dl] && J[i].cm[j] > J[i].cm[dl])))
+                dl = j;
+        if (dl >= 0 && dl != J[i].d) {
+            rc = make_job(jobs[i].section, jobs[i].child, jobs[i].out, &J[i], dl, 0);
+            if (rc) return rc;
+        }
         // the persistent grid's occupancy follows the largest tile's LDS: keep
         // every tile within kBatchLds by taking fewer lines per tile
         if (J[i].lds_bytes > kBatchLds && J[i].G > 1) {
@@ -65,21 +84,43 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
         }
         if (reps) set_child_syms(jobs[i].section, jobs[i].child, &J[i]);
     }
-    // largest sections first: their tiles start early and small ones fill the tail
+    // jobs whose tiles need more than kBatchLds even with one line (long
+    // lines of large classes) go first and to their own launch, so that their
+    // LDS does not set the occupancy of every other tile; within each group,
+    // largest sections first: their tiles start early and small ones fill the
+    // tail
     std::vector<size_t> order(n);
     std::iota(order.begin(), order.end(), 0);
     auto work = [&](size_t i) { return (double)J[i].m[0] * J[i].m[1] * J[i].m[2] * J[i].m[3]; };
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return work(a) > work(b); });
+    auto big = [&](size_t i) { return J[i].lds_bytes > kBatchLds; };
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+        if (big(a) != big(b)) return big(a);
+        return work(a) > work(b);
+    });
     std::vector<SweepJob> S(n);
-    for (size_t i = 0; i < n; i++) S[i] = J[order[i]];
-
-    std::vector<long long> tile_start(n);
-    long long tiles = 0;
-    int lds = 0;
+    int nbig = 0;
     for (size_t i = 0; i < n; i++) {
+        S[i] = J[order[i]];
+        nbig += big(order[i]) ? 1 : 0;
+    }
+
+    // tile numbers start at 0 in each group
+    std::vector<long long> tile_start(n);
+    long long tiles = 0, tiles_big = 0;
+    int lds = 0, lds_big = 0;
+    for (size_t i = 0; i < n; i++) {
+        if ((int)i == nbig) {
+            tiles_big = tiles;
+            tiles = 0;
+        }
         tile_start[i] = tiles;
         tiles += S[i].ntiles;
-        lds = std::max(lds, S[i].lds_bytes);
+        if ((int)i < nbig) lds_big = std::max(lds_big, S[i].lds_bytes);
+        else lds = std::max(lds, S[i].lds_bytes);
+    }
+    if (nbig == (int)n) {
+        tiles_big = tiles;
+        tiles = 0;
     }
     std::vector<int> unit;
     std::vector<long long> chunk_start;
@@ -106,18 +147,22 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
     P->total_tiles = tiles;
     P->total_chunks = chunks;
     P->lds_bytes = lds;
+    P->nbig = nbig;
+    P->tiles_big = tiles_big;
+    P->lds_big = lds_big;
     P->async_alloc = async;
     P->sym = reps;
     int cus = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device);
-    P->grid = std::max(1, cus) * sweep_batch_blocks_per_cu(lds, reps);
+    P->grid = tiles ? std::max(1, cus) * sweep_batch_blocks_per_cu(lds, reps) : 0;
+    P->grid_big = tiles_big ? std::max(1, cus) * sweep_batch_blocks_per_cu(lds_big, reps) : 0;
 
     const size_t o_jobs = 0;
     const size_t o_tiles = align256(o_jobs + n * sizeof(SweepJob));
     const size_t o_unit = align256(o_tiles + n * sizeof(long long));
     const size_t o_chunk = align256(o_unit + unit.size() * sizeof(int) + 4);
     const size_t o_counter = align256(o_chunk + chunk_start.size() * sizeof(long long) + 8);
-    const size_t o_prep = align256(o_counter + 8);
+    const size_t o_prep = align256(o_counter + 16);  // one work counter per launch
     const size_t total = o_prep + prep_total;
     hipError_t e = async ? hipMallocAsync((void **)&P->dev, total, stream) : hipMalloc((void **)&P->dev, total);
     if (e != hipSuccess) { delete P; return hip_fail(e, "plan allocation"); }
@@ -150,13 +195,48 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
     return 0;
 }
 
+// The side stream of the current device (default priority), for the
+// launch of the large-LDS tiles beside the others.
+static hipStream_t side_stream()
+{
+    static std::mutex mu;
+    static hipStream_t st[64];
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!st[dev] && hipStreamCreateWithFlags(&st[dev], hipStreamNonBlocking) != hipSuccess) st[dev] = nullptr;
+    return st[dev];
+}
+
 static int plan_enqueue(pentago_sweep_plan *P, hipStream_t st)
 {
     hipError_t e = launch_prep_batch(P->d_jobs, P->d_unit, P->d_chunk_start, P->nunits,
                                      P->total_chunks, P->T, st);
-    if (e == hipSuccess)
-        e = launch_sweep_batch(P->d_jobs, P->d_tile_start, P->njobs, P->total_tiles, P->lds_bytes,
-                               P->d_counter, P->grid, P->sym, P->T, st);
+    const bool both = P->tiles_big > 0 && P->total_tiles > 0;
+    hipStream_t side = both ? side_stream() : nullptr;
+    if (both && !side) return fail(PENTAGO_EDEVICE, "side stream");
+    hipEvent_t fork = nullptr, join = nullptr;
+    if (e == hipSuccess && both) {
+        e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+    }
+    // the large-LDS tiles on the caller's stream, the others beside them
+    if (e == hipSuccess && P->tiles_big > 0)
+        e = launch_sweep_batch(P->d_jobs, P->d_tile_start, P->nbig, P->tiles_big, P->lds_big, P->d_counter,
+                               P->grid_big, P->sym, P->T, st);
+    if (e == hipSuccess && P->total_tiles > 0)
+        e = launch_sweep_batch(P->d_jobs + P->nbig, P->d_tile_start + P->nbig, P->njobs - P->nbig,
+                               P->total_tiles, P->lds_bytes, P->d_counter + 1, P->grid, P->sym, P->T,
+                               both ? side : st);
+    if (e == hipSuccess && both) {
+        e = hipEventRecord(join, side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);
+    }
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
     if (e != hipSuccess) return hip_fail(e, "batched sweep launch");
     return 0;
 }
@@ -207,9 +287,9 @@ int pentago_plan_launch_graph(pentago_sweep_plan *plan, void *hip_stream)
 int pentago_plan_info(const pentago_sweep_plan *plan, long long *tiles, int *grid, int *lds_bytes)
 {
     if (!plan) return fail(PENTAGO_EINVAL, "plan is NULL");
-    if (tiles) *tiles = plan->total_tiles;
-    if (grid) *grid = plan->grid;
-    if (lds_bytes) *lds_bytes = plan->lds_bytes;
+    if (tiles) *tiles = plan->total_tiles + plan->tiles_big;
+    if (grid) *grid = plan->grid + plan->grid_big;
+    if (lds_bytes) *lds_bytes = std::max(plan->lds_bytes, plan->lds_big);
     return 0;
 }
 

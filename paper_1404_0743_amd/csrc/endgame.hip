@@ -100,10 +100,9 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
     if (GROUP >= 256) __syncthreads();
     else wave_sync();
     const int e = R.e;
-    const uint32_t *nodes = T.dag_node + T.dag_node_off[e];
-    const uint16_t *rank = T.dag_rank + T.dag_rank_off[e];
+    static_assert(kDagEdgeWords == 16, "edge records are two uint4");
+    const uint4 *edges = T.dag_edge + 2 * T.dag_node_off[e];
     const uint16_t *smask = T.dag_sub_mask + T.dag_sub_off[e];
-    const uint16_t *srank = T.dag_sub_rank + T.dag_sub_off[e];
     const int *layer = T.dag_layer[e];
     const int smax = T.dag_sub_max[e];
     // the root mover's stones and the other side's, per quadrant
@@ -117,7 +116,6 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
     for (int t = e; t >= 0; t--) {
         const int n0 = layer[t], n1 = layer[t + 1];
         const int x = (t & 1) ? 3 - R.mover : R.mover;   // side to move at layer t
-        const int xdigit = (t & 1) ? 2 : 1;              // slot digit of x's stones
         // five-set tables of the layer: entries [0, nc) for the root mover's
         // subsets of size ceil(t/2), [smax, smax + no) for the other side's
         const int sc = (t + 1) >> 1, so = t >> 1;
@@ -145,29 +143,29 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
         }
         if (GROUP >= 256) __syncthreads();
         else wave_sync();
+        // the layer's nodes: each node's edge record (two 16-byte loads,
+        // independent of one another) holds its five-set table entries and
+        // the index of the child on each free slot; e - t children per node
+        const int nfree = e - t;
         for (int i = n0 + lane; i < n1; i += GROUP) {
-            const uint32_t nd = nodes[i];
-            const unsigned cmask = nd & 0xffffu, omask = nd >> 16;
-            int code = 0;
-            for (int sl = e - 1; sl >= 0; sl--)
-                code = 3 * code + (((cmask >> sl) & 1) ? 1 : ((omask >> sl) & 1) ? 2 : 0);
-            const Set256 Fc = set_from(ftab + 2 * srank[cmask]);
-            const Set256 Fo = set_from(ftab + 2 * (smax + srank[omask]));
+            const uint4 ra = edges[2 * i], rb = edges[2 * i + 1];
+            const uint32_t w[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
+            const Set256 Fc = set_from(ftab + 2 * (w[0] & 0xffffu));
+            const Set256 Fo = set_from(ftab + 2 * (smax + (w[0] >> 16)));
             const Set256 &Fx = x == R.mover ? Fc : Fo;
             const Set256 &Fy = x == R.mover ? Fo : Fc;
             Set256 Wnt = s_zero(), Nnt = s_zero();
             if (t == e) {
                 Nnt = s_full();
             } else {
-                const unsigned free = ~(cmask | omask) & ((1u << e) - 1u);
-                unsigned f = free;
-                while (f) {
-                    const int sl = __builtin_ctz(f);
-                    f &= f - 1;
-                    const int ci = rank[code + xdigit * (int)c_pow3[sl]];
-                    const uint4 *p = prev + 4 * ci;
-                    s_or_into(Wnt, set_from(p));
-                    s_or_into(Nnt, set_from(p + 2));
+#pragma unroll
+                for (int j = 0; j < 10; j++) {
+                    if (j < nfree) {
+                        const uint32_t ci = (w[1 + (j >> 1)] >> (16 * (j & 1))) & 0xffffu;
+                        const uint4 *p = prev + 4 * ci;
+                        s_or_into(Wnt, set_from(p));
+                        s_or_into(Nnt, set_from(p + 2));
+                    }
                 }
             }
             Set256 W, N;

@@ -19,7 +19,8 @@ struct DevTables {
     const uint32_t *u_ref;      // [4 * 15]
     const uint32_t *dag_node;   // all DAG layouts back to back (cmask | omask << 16)
     const uint16_t *dag_rank;   // all rank tables back to back
-    int dag_node_off[11];       // start of layout e in dag_node
+    const uint4 *dag_edge;      // all per-node edge records back to back (kDagEdgeWords u16 = 2 uint4 each)
+    int dag_node_off[11];       // start of layout e in dag_node (and, in records, in dag_edge)
     int dag_rank_off[11];       // start of layout e in dag_rank
     int dag_layer[11][12];      // layer starts (relative) of layout e
     int dag_max[11];            // largest layer of layout e

@@ -330,6 +330,24 @@ static void build_dag(DagLayout &L, int e)
             }
         L.max_subsets = std::max(L.max_subsets, (int)L.sub_mask.size() - L.sub_start[sz]);
     }
+    // per node: five-set table entries and child indices (the side to move
+    // at layer t is the root's mover for even t, digit 1, else digit 2)
+    L.edge.assign(L.node.size() * kDagEdgeWords, 0);
+    for (int t = 0; t <= e; t++) {
+        const int digit = (t & 1) ? 2 : 1;
+        for (int i = L.layer_start[t]; i < L.layer_start[t + 1]; i++) {
+            const unsigned cm = L.node[i] & 0xffffu, om = L.node[i] >> 16;
+            uint16_t *rec = &L.edge[(size_t)i * kDagEdgeWords];
+            rec[0] = L.sub_rank[cm];
+            rec[1] = L.sub_rank[om];
+            if (t == e) continue;
+            int code = 0;
+            for (int s2 = e - 1; s2 >= 0; s2--) code = 3 * code + ((cm >> s2 & 1) ? 1 : (om >> s2 & 1) ? 2 : 0);
+            int pw = 1, k = 2;
+            for (int sl = 0; sl < e; sl++, pw *= 3)
+                if (!((cm | om) >> sl & 1)) rec[k++] = L.rank[code + digit * pw];
+        }
+    }
     L.sub_start[e + 1] = (int)L.sub_mask.size();
 }
 

@@ -82,7 +82,14 @@ struct DagLayout {
     std::vector<uint16_t> sub_mask, sub_rank;
     std::vector<int> sub_start;
     int max_subsets;                // largest C(e, s)
+    // per node (layer order), kDagEdgeWords u16: the ranks of cmask and
+    // omask among the subsets of their sizes (their five-set table entries),
+    // then the index in layer t + 1 of the child on each free slot, in
+    // increasing slot order; unused words are 0
+    std::vector<uint16_t> edge;
 };
+
+constexpr int kDagEdgeWords = 16;
 
 const DagLayout &dag_layout(int e);
 
