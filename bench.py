@@ -110,14 +110,6 @@ def parity_sample(entries, n=4096):
     return offs, O.section_solve(SECTION, [None] * 4, all_idx[offs], nthreads=host_cpu()["threads"])
 
 
-def _blob_sha(path):
-    """git's blob hash of a file (identifies the kernel source a profile was taken on)."""
-    import hashlib
-    with open(path, "rb") as f:
-        data = f.read()
-    return hashlib.sha1(b"blob %d\0" % len(data) + data).hexdigest()
-
-
 VALU_PEAK = 256 * 4 * 2.4e9 / 4   # wave64 VALU instructions/s: 256 CUs x 4 SIMD16 at 2.4 GHz
 
 
@@ -143,16 +135,9 @@ def profile_counts(name):
 def measured_traffic():
     """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, scaled by the copy-kernel calibration it records;
-    None when the kernel source has changed since the counters were taken."""
-    tfile = os.path.join(ROOT, "profiles", "sweep_kernel_section_36to35_traffic.json")
-    if not os.path.exists(tfile):
-        return None
-    with open(tfile) as f:
-        t = json.load(f)
-    src = os.path.join(ROOT, t.get("kernel_source", ""))
-    if not os.path.exists(src) or _blob_sha(src) != t.get("kernel_source_blob"):
-        return None
-    return t.get("bytes_per_launch")
+    None when the kernel sources have changed since the counters were taken."""
+    d = profile_counts("sweep_kernel_section_36to35_traffic")
+    return None if d is None else d.get("bytes_per_launch")
 
 
 def roofline_valu(avg_ms):

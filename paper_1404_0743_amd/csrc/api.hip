@@ -75,7 +75,7 @@ int device_tables(DevTables *out)
         size_t bytes;
         void **dst;
     };
-    void *canon, *qinfo, *lm, *dn, *dr, *sel, *cref, *uref, *smask, *srank, *symmap, *symcode, *dedge;
+    void *canon, *qinfo, *lm, *dn, *dr, *sel, *cref, *uref, *smask, *srank, *symmap, *symcode, *syminv, *dedge;
     Up ups[] = {{H.canon.data(), H.canon.size() * 2, &canon},
                 {H.qinfo.data(), H.qinfo.size() * sizeof(QInfo), &qinfo},
                 {H.lm.data(), H.lm.size() * sizeof(LineMasks), &lm},
@@ -88,6 +88,7 @@ int device_tables(DevTables *out)
                 {subrank.data(), subrank.size() * 2, &srank},
                 {H.symmap.data(), H.symmap.size() * 2, &symmap},
                 {H.symcode.data(), H.symcode.size() * 2, &symcode},
+                {H.syminv.data(), H.syminv.size() * 2, &syminv},
                 {edges.data(), edges.size() * 2, &dedge}};
     for (Up &u : ups) {
         e = hipMalloc(&p, u.bytes);
@@ -109,6 +110,7 @@ int device_tables(DevTables *out)
     T.dag_sub_rank = (const uint16_t *)srank;
     T.symmap = (const uint16_t *)symmap;
     T.symcode = (const uint16_t *)symcode;
+    T.syminv = (const uint16_t *)syminv;
     g_dev_tables[dev] = T;
     *out = T;
     return 0;

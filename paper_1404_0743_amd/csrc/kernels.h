@@ -31,6 +31,7 @@ struct DevTables {
     int dag_sub_max[11];        // largest C(e, s)
     const uint16_t *symmap;     // [8 * kPatterns]: source pattern | turns << 12 per symmetry
     const uint16_t *symcode;    // [8 * 19683]: preimage of a quadrant code under each symmetry
+    const uint16_t *syminv;     // [8 * kPatterns]: image pattern per source pattern (inverse of symmap)
 };
 
 // The table of the image section sym(s) from the table of s (Section III,

@@ -11,17 +11,24 @@
 
 namespace pg {
 
-// One workgroup takes a quarter of one 8^4 block of the image section (up to
-// 1024 entries; each wave 64 entries per step).  The block's entries are
-// enumerated with image dimension 3 fastest and next the image dimension A
-// that receives the source's dimension 3 (for symmetries that keep
-// dimension 3 in place, dimension 2): so the two entries of a 128-byte
-// source line, neighbours along source dimension 3, are read in the same
-// step (for the rotations; a reflection also reorders the patterns inside
-// each dimension, and can separate them), while each store instruction
-// still writes runs of eight neighbouring image entries.  Lane i works on
-// entry 16 (i & 3) + (i >> 2) of its wave's 64: it finds its source entry,
-// the quad loads its four source entries whole, transposes, transforms,
+// One workgroup takes a quarter of one 8^4 tile of the image section (up to
+// 1024 entries; each wave 64 entries per step).  For the rotations a tile is
+// an image block.  A reflection also permutes the patterns of every class
+// (the mirror image of a rotation-minimal pattern is canonicalised again),
+// so the eight image entries of a block along the image dimension G that
+// receives the source's dimension 3 come from eight scattered source
+// entries, and the other half of each 128-byte source line would be read by
+// another workgroup.  For the reflections the tile therefore takes along G
+// the image patterns whose sources form one source block along dimension 3
+// (the inverse map syminv), and the image entries along G land in several
+// image blocks, each written whole (64 bytes).  The tile's entries are
+// enumerated with image dimension 3 fastest and next the dimension A = G
+// (for symmetries that keep dimension 3 in place, dimension 2): so the two
+// halves of every source line are read by one load instruction (halves
+// read by different instructions, even of the same workgroup, are fetched
+// from HBM twice).  Lane i works on entry
+// 16 (i & 3) + (i >> 2) of its wave's 64: it finds its source entry, the
+// quad loads its four source entries whole, transposes, transforms,
 // transposes back and stores its four image entries whole.
 template <int SYM>
 __global__ void __launch_bounds__(256) transform_kernel(SymJob J, DevTables T)
@@ -33,7 +40,9 @@ __global__ void __launch_bounds__(256) transform_kernel(SymJob J, DevTables T)
     const int quarter = (int)(k & 3u);
     if (blk >= J.nblocks) return;
     // enumeration order of the block's dimensions, slowest first
-    constexpr int A = sym_quadrant(SYM, 3) == 3 ? 2 : sym_quadrant(SYM, 3);
+    constexpr int G = sym_quadrant(SYM, 3);
+    constexpr bool GROUP = (SYM & 4) != 0;  // tile along G by source blocks
+    constexpr int A = G == 3 ? 2 : G;
     constexpr int O1 = A == 0 ? 1 : 0;
     constexpr int O2 = (A == 2 || O1 == 2) ? (A == 1 || O1 == 1 ? 0 : 1) : 2;
     constexpr int D0 = O1 < O2 ? O1 : O2, D1 = O1 < O2 ? O2 : O1;
@@ -52,6 +61,21 @@ __global__ void __launch_bounds__(256) transform_kernel(SymJob J, DevTables T)
     }
     const uint32_t base = block_offset(J.m, corner);
     const int vol = s[0] * s[1] * s[2] * s[3];
+    // reflections: per entry t of the tile along G, the image pattern's block
+    // offset with the tile's other corners, and its local index, its block's
+    // extent along G and its symmap entry (r | s << 3 | map << 8)
+    __shared__ uint32_t gbase[8], ginfo[8];
+    if constexpr (GROUP) {
+        if ((int)threadIdx.x < s[G]) {
+            const int ig = T.syminv[SYM * kPatterns + J.qb[G] + corner[G] + (int)threadIdx.x];
+            int c2[4] = {corner[0], corner[1], corner[2], corner[3]};
+            c2[G] = ig & ~7;
+            gbase[threadIdx.x] = block_offset(J.m, c2);
+            ginfo[threadIdx.x] = (uint32_t)(ig & 7) | ((uint32_t)min(8, J.m[G] - (ig & ~7)) << 3) |
+                                 ((uint32_t)T.symmap[SYM * kPatterns + J.qb[G] + ig] << 8);
+        }
+        __syncthreads();
+    }
     const int end = min(vol, 1024 * (quarter + 1));
     // r / s for r < 4096 and s <= 8 as a multiply-high by ceil(2^16 / s):
     // the error stays below 1/16, under the 1/s gap to the next integer
@@ -73,11 +97,21 @@ __global__ void __launch_bounds__(256) transform_kernel(SymJob J, DevTables T)
         int sidx[4], h[4];
 #pragma unroll
         for (int j = 0; j < 4; j++) {
-            const uint32_t e = map[J.qb[j] + corner[j] + loc[j]];
+            // along G (reflections) the tile's entry loc[G] comes from LDS
+            const uint32_t e = (GROUP && j == G) ? ginfo[loc[G]] >> 8 : map[J.qb[j] + corner[j] + loc[j]];
             h[j] = (int)(e >> 12);
             sidx[sym_source(SYM, j)] = (int)(e & 0xfffu);
         }
-        const uint32_t doff = base + (uint32_t)(((loc[0] * s[1] + loc[1]) * s[2] + loc[2]) * s[3] + loc[3]);
+        uint32_t doff;
+        if constexpr (GROUP) {
+            const uint32_t gi = ginfo[loc[G]];
+            int l[4] = {loc[0], loc[1], loc[2], loc[3]}, t[4] = {s[0], s[1], s[2], s[3]};
+            l[G] = (int)(gi & 7u);
+            t[G] = (int)((gi >> 3) & 15u);
+            doff = gbase[loc[G]] + (uint32_t)(((l[0] * t[1] + l[1]) * t[2] + l[2]) * t[3] + l[3]);
+        } else {
+            doff = base + (uint32_t)(((loc[0] * s[1] + loc[1]) * s[2] + loc[2]) * s[3] + loc[3]);
+        }
         const uint32_t off = block_offset(J.sm, sidx);
         const uint32_t offs[4] = {quad_perm<0x00>(off), quad_perm<0x55>(off), quad_perm<0xAA>(off),
                                   quad_perm<0xFF>(off)};

@@ -231,6 +231,18 @@ static void build_symmetry(HostTables &t)
                 }
             }
     }
+    // the inverse permutation of each class under each symmetry
+    t.syminv.assign(8 * kPatterns, 0xffff);
+    for (int sym = 0; sym < 8; sym++)
+        for (int b = 0; b <= 9; b++)
+            for (int w = 0; b + w <= 9; w++) {
+                const int start = t.class_start[b][w];
+                for (int i = 0; i < t.class_size[b][w]; i++) {
+                    uint16_t &slot = t.syminv[sym * kPatterns + start + (t.symmap[sym * kPatterns + start + i] & 0xfff)];
+                    if (slot != 0xffff) throw std::logic_error("symmetry map is not a permutation");
+                    slot = (uint16_t)i;
+                }
+            }
 }
 
 static void build(HostTables &t)

@@ -39,6 +39,10 @@ struct HostTables {
     // the source pattern whose local image is a turn of pattern i, | h << 12,
     // where that local image is pattern i turned h more times (h = 0..3).
     std::vector<uint16_t> symmap;  // [8 * kPatterns]
+    // syminv[sym * kPatterns + start + u]: the pattern i of the class starting
+    // at start whose symmap entry names source pattern u (symmap is a
+    // permutation of each class)
+    std::vector<uint16_t> syminv;  // [8 * kPatterns]
     // symcode[sym * 19683 + c]: the quadrant code that the local map of
     // symmetry sym takes to c (its preimage: mirror^f of c turned -r times).
     std::vector<uint16_t> symcode;  // [8 * 19683]
