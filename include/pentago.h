@@ -209,10 +209,13 @@ typedef struct {
     pentago_superinfo *out;
 } pentago_section_job;
 
-/* Many sections of one slice (all the same stone count) in one persistent
- * launch, work-balanced across the GPU by a device work queue.  Results are
- * bit-identical to calling pentago_solve_section on each job.  Jobs must not
- * write to any table another job of the same call reads.  n <= 65536. */
+/* Many sections of one slice (all the same stone count) in one launch: the
+ * tiles of every job form one grid (jobs whose tiles need more than 52 KiB of
+ * LDS take a second launch beside it), after one batched prep launch for
+ * children along dimensions that are not staged.  Results are bit-identical
+ * to calling pentago_solve_section on each job.  Jobs must not write to any
+ * table another job of the same call reads.  n <= 65536; ERANGE when a launch
+ * would exceed 2^31 - 1 tiles. */
 int pentago_solve_sections(const pentago_section_job *jobs, size_t n, void *hip_stream);
 
 /* The same with every job's children held as their representatives under
@@ -232,13 +235,14 @@ int pentago_plan_create(const pentago_section_job *jobs, size_t n, pentago_sweep
 /* A plan whose jobs' children are representatives (as pentago_solve_sections_d4). */
 int pentago_plan_create_d4(const pentago_section_job *jobs, size_t n, pentago_sweep_plan **plan);
 /* Enqueue the layer on hip_stream: one batched prep launch (children along
- * dimensions that are not staged) and one persistent sweep launch. */
+ * dimensions that are not staged) and the sweep launch(es). */
 int pentago_plan_launch(pentago_sweep_plan *plan, void *hip_stream);
 /* The same work as one hipGraph: captured on the plan's own stream at the
  * first call, replayed on hip_stream at every call.  Launches of one plan
  * must not overlap. */
 int pentago_plan_launch_graph(pentago_sweep_plan *plan, void *hip_stream);
-/* Work tiles of the layer, persistent grid size and LDS bytes per workgroup. */
+/* Work tiles of the layer, workgroups launched (one per tile) and the
+ * largest LDS bytes per workgroup. */
 int pentago_plan_info(const pentago_sweep_plan *plan, long long *tiles, int *grid, int *lds_bytes);
 /* Waits for the plan's work, then releases it. */
 int pentago_plan_destroy(pentago_sweep_plan *plan);

@@ -1,7 +1,7 @@
-// batch.hip -- many sections of one slice in one persistent launch (the
-// whole layer's block lines as one work queue, Section IV-A's "each process
-// computes its block lines in any order" on one GPU), plus the sweep plan that
-// keeps the layer's job table resident and replays it from a hipGraph.
+// batch.hip -- many sections of one slice in one launch (the whole layer's
+// block lines as one grid of tiles, Section IV-A's "each process computes its
+// block lines in any order" on one GPU), plus the sweep plan that keeps the
+// layer's job table resident and replays it from a hipGraph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,18 +18,17 @@ struct pentago_sweep_plan {
     int device = 0;
     int njobs = 0, nunits = 0;
     long long total_tiles = 0, total_chunks = 0;
-    int lds_bytes = 0, grid = 0;
+    int lds_bytes = 0;
     // jobs [0, nbig) have tiles above kBatchLds of LDS even with one line;
-    // they take a second persistent launch, beside the first on a side stream
+    // they take a second launch, beside the first on a side stream
     int nbig = 0;
     long long tiles_big = 0;
-    int lds_big = 0, grid_big = 0;
-    char *dev = nullptr;  // one device block: jobs, tile starts, units, chunk starts, counter, prep
+    int lds_big = 0;
+    char *dev = nullptr;  // one device block: jobs, tile starts, units, chunk starts, prep
     SweepJob *d_jobs = nullptr;
     long long *d_tile_start = nullptr;
     int *d_unit = nullptr;
     long long *d_chunk_start = nullptr;
-    unsigned long long *d_counter = nullptr;
     bool async_alloc = false;
     bool sym = false;  // children held as their representatives
     hipStream_t capture = nullptr;
@@ -42,8 +41,9 @@ namespace pg {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// LDS bound of one batched tile (bytes).
-constexpr int kBatchLds = 40960;
+// LDS bound of one batched tile (bytes): three workgroups per CU, the
+// headline tile shape (7 lines of 160 patterns) included.
+constexpr int kBatchLds = 53248;
 
 // Build a plan: job table in decreasing order of work, prep units for the
 // dimensions that are not staged, and the device block holding all of it.
@@ -73,8 +73,8 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
             rc = make_job(jobs[i].section, jobs[i].child, jobs[i].out, &J[i], dl, 0);
             if (rc) return rc;
         }
-        // the persistent grid's occupancy follows the largest tile's LDS: keep
-        // every tile within kBatchLds by taking fewer lines per tile
+        // a launch's occupancy follows its largest tile's LDS: keep every
+        // tile within kBatchLds by taking fewer lines per tile
         if (J[i].lds_bytes > kBatchLds && J[i].G > 1) {
             int G = J[i].G;
             const int cmd = (J[i].emask >> J[i].d) & 1 ? J[i].cm[J[i].d] : 0;
@@ -122,6 +122,8 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
         tiles_big = tiles;
         tiles = 0;
     }
+    if (tiles > 0x7fffffffLL || tiles_big > 0x7fffffffLL)
+        return fail(PENTAGO_ERANGE, "more than 2^31 - 1 tiles in one launch");
     std::vector<int> unit;
     std::vector<long long> chunk_start;
     std::vector<size_t> prep_off;
@@ -152,17 +154,12 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
     P->lds_big = lds_big;
     P->async_alloc = async;
     P->sym = reps;
-    int cus = 0;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device);
-    P->grid = tiles ? std::max(1, cus) * sweep_batch_blocks_per_cu(lds, reps) : 0;
-    P->grid_big = tiles_big ? std::max(1, cus) * sweep_batch_blocks_per_cu(lds_big, reps) : 0;
 
     const size_t o_jobs = 0;
     const size_t o_tiles = align256(o_jobs + n * sizeof(SweepJob));
     const size_t o_unit = align256(o_tiles + n * sizeof(long long));
     const size_t o_chunk = align256(o_unit + unit.size() * sizeof(int) + 4);
-    const size_t o_counter = align256(o_chunk + chunk_start.size() * sizeof(long long) + 8);
-    const size_t o_prep = align256(o_counter + 16);  // one work counter per launch
+    const size_t o_prep = align256(o_chunk + chunk_start.size() * sizeof(long long) + 8);
     const size_t total = o_prep + prep_total;
     hipError_t e = async ? hipMallocAsync((void **)&P->dev, total, stream) : hipMalloc((void **)&P->dev, total);
     if (e != hipSuccess) { delete P; return hip_fail(e, "plan allocation"); }
@@ -170,7 +167,6 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
     P->d_tile_start = (long long *)(P->dev + o_tiles);
     P->d_unit = (int *)(P->dev + o_unit);
     P->d_chunk_start = (long long *)(P->dev + o_chunk);
-    P->d_counter = (unsigned long long *)(P->dev + o_counter);
     size_t u = 0;
     for (size_t i = 0; i < n; i++)
         for (int j = 0; j < 4; j++) {
@@ -180,7 +176,7 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
             S[i].prep_out[j] = p;
         }
     // one host image of the table block, copied in one transfer
-    std::vector<char> img(o_counter, 0);
+    std::vector<char> img(o_prep, 0);
     memcpy(img.data() + o_jobs, S.data(), n * sizeof(SweepJob));
     memcpy(img.data() + o_tiles, tile_start.data(), n * sizeof(long long));
     if (!unit.empty()) {
@@ -225,12 +221,10 @@ static int plan_enqueue(pentago_sweep_plan *P, hipStream_t st)
     }
     // the large-LDS tiles on the caller's stream, the others beside them
     if (e == hipSuccess && P->tiles_big > 0)
-        e = launch_sweep_batch(P->d_jobs, P->d_tile_start, P->nbig, P->tiles_big, P->lds_big, P->d_counter,
-                               P->grid_big, P->sym, P->T, st);
+        e = launch_sweep_batch(P->d_jobs, P->d_tile_start, P->nbig, P->tiles_big, P->lds_big, P->sym, P->T, st);
     if (e == hipSuccess && P->total_tiles > 0)
         e = launch_sweep_batch(P->d_jobs + P->nbig, P->d_tile_start + P->nbig, P->njobs - P->nbig,
-                               P->total_tiles, P->lds_bytes, P->d_counter + 1, P->grid, P->sym, P->T,
-                               both ? side : st);
+                               P->total_tiles, P->lds_bytes, P->sym, P->T, both ? side : st);
     if (e == hipSuccess && both) {
         e = hipEventRecord(join, side);
         if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);
@@ -288,7 +282,7 @@ int pentago_plan_info(const pentago_sweep_plan *plan, long long *tiles, int *gri
 {
     if (!plan) return fail(PENTAGO_EINVAL, "plan is NULL");
     if (tiles) *tiles = plan->total_tiles + plan->tiles_big;
-    if (grid) *grid = plan->grid + plan->grid_big;
+    if (grid) *grid = (int)std::min<long long>(plan->total_tiles + plan->tiles_big, 0x7fffffff);
     if (lds_bytes) *lds_bytes = std::max(plan->lds_bytes, plan->lds_big);
     return 0;
 }

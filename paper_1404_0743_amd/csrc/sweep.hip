@@ -642,69 +642,63 @@ __global__ void __launch_bounds__(NT, NT == 512 ? (SYMC ? 5 : 6) : 1) sweep_kern
     sweep_tile<D, SYMC>(J, T, tile, (void *)lds);
 }
 
-// Many sections in one persistent launch: workgroups take tiles from a
-// device counter; tile_start[j] is the first global tile of job j.
-// Persistent loop of the batched sweep: workgroups take tiles from the
-// device counter until the layer is done.  SYMS: some staged children are
-// held as their representatives (sweep_tile<D, true> for those jobs).
+// Many sections in one launch: workgroup b takes global tile b, found in
+// the job whose tiles start at tile_start[j] <= b.  The hardware dispatcher
+// hands out the tiles (measured faster than a persistent grid pulling tiles
+// from a device counter: no queue atomic, no job table re-read per tile, and
+// a new workgroup starts as soon as one ends).  SYMS: some staged children
+// are held as their representatives (sweep_tile<D, true> for those jobs).
 template <bool SYMS>
-__device__ __forceinline__ void sweep_batch_loop(const SweepJob *jobs, const long long *tile_start, int njobs,
-                                 long long total, unsigned long long *counter, const DevTables &T)
+__device__ __forceinline__ void sweep_batch_tile(const SweepJob *jobs, const long long *tile_start, int njobs,
+                                                 long long total, const DevTables &T)
 {
     extern __shared__ uint4 lds[];
-    __shared__ long long s_tile;
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = (long long)atomicAdd(counter, 1ull);
-        __syncthreads();
-        const long long t = s_tile;
-        __syncthreads();
-        if (t >= total) break;
-        int lo = 0, hi = njobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tile_start[mid] <= t) lo = mid;
-            else hi = mid - 1;
+    const long long t = blockIdx.x;
+    if (t >= total) return;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile_start[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const SweepJob &J = jobs[lo];
+    const long long local = t - tile_start[lo];
+    const bool symc = SYMS && J.csym[J.d] != 0 && ((J.emask >> J.d) & 1) && !((J.odmask >> J.d) & 1);
+    if (J.emask == 0) {
+        sweep_tile<3, false, false>(J, T, local, (void *)lds);  // full boards
+    } else if (symc) {
+        switch (J.d) {
+        case 0: sweep_tile<0, SYMS>(J, T, local, (void *)lds); break;
+        case 1: sweep_tile<1, SYMS>(J, T, local, (void *)lds); break;
+        case 2: sweep_tile<2, SYMS>(J, T, local, (void *)lds); break;
+        default: sweep_tile<3, SYMS>(J, T, local, (void *)lds); break;
         }
-        const SweepJob &J = jobs[lo];
-        const long long local = t - tile_start[lo];
-        const bool symc = SYMS && J.csym[J.d] != 0 && ((J.emask >> J.d) & 1) && !((J.odmask >> J.d) & 1);
-        if (J.emask == 0) {
-            sweep_tile<3, false, false>(J, T, local, (void *)lds);  // full boards
-        } else if (symc) {
-            switch (J.d) {
-            case 0: sweep_tile<0, SYMS>(J, T, local, (void *)lds); break;
-            case 1: sweep_tile<1, SYMS>(J, T, local, (void *)lds); break;
-            case 2: sweep_tile<2, SYMS>(J, T, local, (void *)lds); break;
-            default: sweep_tile<3, SYMS>(J, T, local, (void *)lds); break;
-            }
-        } else {
-            switch (J.d) {
-            case 0: sweep_tile<0>(J, T, local, (void *)lds); break;
-            case 1: sweep_tile<1>(J, T, local, (void *)lds); break;
-            case 2: sweep_tile<2>(J, T, local, (void *)lds); break;
-            default: sweep_tile<3>(J, T, local, (void *)lds); break;
-            }
+    } else {
+        switch (J.d) {
+        case 0: sweep_tile<0>(J, T, local, (void *)lds); break;
+        case 1: sweep_tile<1>(J, T, local, (void *)lds); break;
+        case 2: sweep_tile<2>(J, T, local, (void *)lds); break;
+        default: sweep_tile<3>(J, T, local, (void *)lds); break;
         }
-        __syncthreads();
     }
 }
 
-__global__ void __launch_bounds__(256)
-    sweep_batch_kernel(const SweepJob *jobs, const long long *tile_start, int njobs,
-                       long long total, unsigned long long *counter, DevTables T)
+// 512 threads, at least 6 (5 with the symmetry variants) waves per SIMD:
+// three workgroups of tiles up to 52 KiB of LDS per CU, as the tuned
+// single-section sweep
+__global__ void __launch_bounds__(512, 6)
+    sweep_batch_kernel(const SweepJob *jobs, const long long *tile_start, int njobs, long long total, DevTables T)
 {
-    sweep_batch_loop<false>(jobs, tile_start, njobs, total, counter, T);
+    sweep_batch_tile<false>(jobs, tile_start, njobs, total, T);
 }
 
 // The same over jobs whose children may be held as their representatives.
-__global__ void __launch_bounds__(256)
-    sweep_batch_sym_kernel(const SweepJob *jobs, const long long *tile_start, int njobs,
-                           long long total, unsigned long long *counter, DevTables T)
+__global__ void __launch_bounds__(512, 5)
+    sweep_batch_sym_kernel(const SweepJob *jobs, const long long *tile_start, int njobs, long long total,
+                           DevTables T)
 {
-    sweep_batch_loop<true>(jobs, tile_start, njobs, total, counter, T);
+    sweep_batch_tile<true>(jobs, tile_start, njobs, total, T);
 }
-
-
 
 hipError_t launch_prep(const SweepJob &job, int j, const DevTables &T, hipStream_t s)
 {
@@ -779,26 +773,18 @@ hipError_t launch_prep_batch(const SweepJob *dev_jobs, const int *dev_unit,
     return hipGetLastError();
 }
 
-int sweep_batch_blocks_per_cu(int lds_bytes, bool sym)
-{
-    int n = 0;
-    const hipError_t e = sym ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_batch_sym_kernel, 256, lds_bytes)
-                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_batch_kernel, 256, lds_bytes);
-    if (e != hipSuccess) return 1;
-    return std::max(1, n);
-}
-
 hipError_t launch_sweep_batch(const SweepJob *dev_jobs, const long long *dev_tile_start, int njobs,
-                              long long total_tiles, int lds_bytes, unsigned long long *dev_counter,
-                              int grid, bool sym, const DevTables &T, hipStream_t s)
+                              long long total_tiles, int lds_bytes, bool sym, const DevTables &T, hipStream_t s)
 {
-    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, dev_counter, 1);
+    if (total_tiles <= 0) return hipSuccess;
+    if (total_tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)total_tiles), block(kBatchThreads);
     if (sym)
-        hipLaunchKernelGGL(sweep_batch_sym_kernel, dim3(grid), dim3(256), lds_bytes, s, dev_jobs,
-                           dev_tile_start, njobs, total_tiles, dev_counter, T);
+        hipLaunchKernelGGL(sweep_batch_sym_kernel, grid, block, lds_bytes, s, dev_jobs, dev_tile_start, njobs,
+                           total_tiles, T);
     else
-        hipLaunchKernelGGL(sweep_batch_kernel, dim3(grid), dim3(256), lds_bytes, s, dev_jobs,
-                           dev_tile_start, njobs, total_tiles, dev_counter, T);
+        hipLaunchKernelGGL(sweep_batch_kernel, grid, block, lds_bytes, s, dev_jobs, dev_tile_start, njobs,
+                           total_tiles, T);
     return hipGetLastError();
 }
 
