@@ -7,7 +7,7 @@
                  per empties group (pentago_eval_batch_grouped).
   layers         64 sections per slice for slices 35, 34, 33 (sizes 1e4..2e8
                  positions, stratified by size), child chains solved first
-                 (untimed): one persistent launch per layer replayed from a
+                 (untimed): one batched launch per layer replayed from a
                  hipGraph against 64 per-section launches.
   serving        an open-loop Poisson stream of 2^17 queries with 26..33
                  stones (first 4096 dropped as warm-up) against the server

@@ -1,7 +1,8 @@
 // batch.hip -- many sections of one slice in one launch (the whole layer's
-// block lines as one grid of tiles, Section IV-A's "each process computes its
-// block lines in any order" on one GPU), plus the sweep plan that keeps the
-// layer's job table resident and replays it from a hipGraph.
+// block lines as one grid of tiles: within a slice the block lines are
+// independent and may be computed in any order, Section IV-A), plus the sweep
+// plan that keeps the layer's job table resident and replays it from a
+// hipGraph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -36,7 +36,7 @@ def slice_jobs(stones, reps_above):
 
 def solve_slice(stones, reps_above=None, stream=None):
     """Tables of every D4-minimal section of the slice (dict counts -> table),
-    enqueued on `stream` as one persistent launch."""
+    enqueued on `stream` as one batched launch."""
     if not 0 <= stones <= 35:
         raise ValueError("slices of 0..35 stones (36-stone boards are evaluated on demand)")
     jobs, tables = slice_jobs(stones, reps_above)
@@ -95,7 +95,7 @@ def solve_slice_streamed(stones, reps_above, sink, out_budget=64 << 30, prep_bud
                          stream=None, events=None):
     """Every D4-minimal section of a slice whose tables do not fit in HBM
     together (slice 33: 337.8 GB), solved in batches through one arena of
-    out_budget bytes: each batch is one persistent launch
+    out_budget bytes: each batch is one batched launch
     (pentago_solve_sections_d4) whose tables are views of the arena; after
     it, sink(tables) is called (tables: counts -> device view, valid until
     sink returns; work sink enqueues on the stream is ordered before the next

@@ -1,4 +1,4 @@
-"""GPU parity of the batched forms: pentago_solve_sections (one persistent
+"""GPU parity of the batched forms: pentago_solve_sections (one batched
 launch over many sections of one slice) and the sweep plan launched directly
 and from a captured hipGraph must give the bytes of the per-section sweep,
 which itself is checked against the oracle (O4) on sampled entries here."""

@@ -10,7 +10,7 @@ on samples of the computed slices), bit for bit (tolerance 0):
                           subset of 4096 against O2 (minimax), the rest against
                           the per-group launches;
   uneven layers 35/34/33  64 sections per layer (seed 1404074304 + layer):
-                          the persistent launch, the plan launched directly and
+                          the batched launch, the plan launched directly and
                           replayed from its hipGraph give the same bytes, and
                           sampled entries of every section equal O2 on the
                           concrete boards (and O4 for layer 35);
