@@ -75,7 +75,7 @@ int device_tables(DevTables *out)
         size_t bytes;
         void **dst;
     };
-    void *canon, *qinfo, *lm, *dn, *dr, *sel, *cref, *uref, *smask, *srank, *symmap, *symcode, *syminv, *dedge;
+    void *canon, *qinfo, *lm, *dn, *dr, *sel, *cref, *uref, *smask, *srank, *symmap, *symcode, *syminv, *dedge, *plm, *psel, *pch;
     Up ups[] = {{H.canon.data(), H.canon.size() * 2, &canon},
                 {H.qinfo.data(), H.qinfo.size() * sizeof(QInfo), &qinfo},
                 {H.lm.data(), H.lm.size() * sizeof(LineMasks), &lm},
@@ -89,6 +89,9 @@ int device_tables(DevTables *out)
                 {H.symmap.data(), H.symmap.size() * 2, &symmap},
                 {H.symcode.data(), H.symcode.size() * 2, &symcode},
                 {H.syminv.data(), H.syminv.size() * 2, &syminv},
+                {H.pat_lm.data(), H.pat_lm.size() * sizeof(LineMasks), &plm},
+                {H.pat_sel.data(), H.pat_sel.size() * 4, &psel},
+                {H.pat_child.data(), H.pat_child.size() * sizeof(PosChild), &pch},
                 {edges.data(), edges.size() * 2, &dedge}};
     for (Up &u : ups) {
         e = hipMalloc(&p, u.bytes);
@@ -111,6 +114,9 @@ int device_tables(DevTables *out)
     T.symmap = (const uint16_t *)symmap;
     T.symcode = (const uint16_t *)symcode;
     T.syminv = (const uint16_t *)syminv;
+    T.pat_lm = (const LineMasks *)plm;
+    T.pat_sel = (const uint4 *)psel;
+    T.pat_child = (const PosChild *)pch;
     g_dev_tables[dev] = T;
     *out = T;
     return 0;

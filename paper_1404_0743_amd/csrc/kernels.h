@@ -32,6 +32,9 @@ struct DevTables {
     const uint16_t *symmap;     // [8 * kPatterns]: source pattern | turns << 12 per symmetry
     const uint16_t *symcode;    // [8 * 19683]: preimage of a quadrant code under each symmetry
     const uint16_t *syminv;     // [8 * kPatterns]: image pattern per source pattern (inverse of symmap)
+    const LineMasks *pat_lm;    // per-pattern lookups of the tile set-up (HostTables)
+    const uint4 *pat_sel;
+    const PosChild *pat_child;
 };
 
 // The table of the image section sym(s) from the table of s (Section III,

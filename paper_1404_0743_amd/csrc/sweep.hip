@@ -104,7 +104,7 @@ __device__ __forceinline__ void child_entry_terms(const SweepJob &J, const DevTa
 // split into the three chunks of quadrant D's LineMasks (6 slots each), and
 // each chunk gets a 64-entry table over subsets of its lines, so F[k] is
 // three table reads.  The selectors (which lines D completes at k) depend
-// only on D's pattern and come from T.sel.
+// only on D's pattern and come from T.pat_sel (T.sel per pattern).
 // ---------------------------------------------------------------------------
 
 // LDS layout of one tile.  Per tile: the selectors of every position along D
@@ -120,9 +120,6 @@ constexpr int kOSlots = 19;                    // 18 chunk lines + U
 constexpr int kLutStride = 2 * 3 * 64 + 1;    // uint2 per line; +1 staggers the banks of lines
 constexpr int kRecWords = 18;
 
-struct PosChild {
-    uint16_t nchild, child[9];   // child index | k << 12 per empty cell
-};
 struct ChildPosRec {
     uint4 sel_c, sel_o;
 };
@@ -378,6 +375,16 @@ __device__ __forceinline__ void sweep_tile(const SweepJob &J, const DevTables &T
     int cshape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
     cshape[D] = cmD;
 
+    // The line references of this thread's first partial-set item (below)
+    // are fetched now, so that their latency overlaps phase 0.
+    auto item_refs = [&](int it) -> uint32_t {
+        const int l = it - 33 * (int)(((uint32_t)it * 1986u) >> 16);
+        // chunk slots carry two references (0xffff: unused slot), the lines
+        // missing D three
+        return l < 18 ? (uint32_t)T.chunk_ref[D * 18 + l] | 0xff0000u : T.u_ref[D * 15 + (l - 18)];
+    };
+    const uint32_t refs0 = (int)threadIdx.x < nlines * 2 * 33 ? item_refs(threadIdx.x) : 0u;
+
     // The first child item of this thread is fetched from HBM now, so its
     // latency overlaps the table set-up below.
     uint4 pre[4] = {};
@@ -396,14 +403,14 @@ __device__ __forceinline__ void sweep_tile(const SweepJob &J, const DevTables &T
     // Phase 0: per-line tables (LineMasks of the fixed quadrants, partial
     // sets, chunk tables), for both colours, and the per-position records.
     // Every work item is one small uniform task: a LineMasks, a position, one
-    // line's cylinder product, one chunk table entry.
+    // line's cylinder product, one chunk table entry.  The per-pattern
+    // lookups come from tables indexed by pattern (one load each).
     for (int it = threadIdx.x; it < nlines * 8; it += blockDim.x) {
         const int v = it >> 3, x = ((it >> 2) & 1) + 1, j = it & 3;
         const int ij = get4(base, j) + (j == E ? v : 0);
         const int qbj = j == 0 ? J.qb[0] : j == 1 ? J.qb[1] : j == 2 ? J.qb[2] : J.qb[3];
-        const QInfo q = T.qinfo[j == D ? 0 : qbj + ij];
-        const LineMasks lm = T.lm[j * 512 + (x == 1 ? q.bm : q.wm)];
         const bool keep = j != D;
+        const LineMasks lm = T.pat_lm[((j * kPatterns + (keep ? qbj + ij : 0)) << 1) + x - 1];
         L.lmq[it] = LineMasks{keep ? lm.a : 0u, keep ? lm.b : 0u, keep ? lm.c : 0u};
         if ((it & 7) == 0) {
             Idx4 li = base;
@@ -416,29 +423,23 @@ __device__ __forceinline__ void sweep_tile(const SweepJob &J, const DevTables &T
     const int npos = mD + (staged ? cmD : 0);
     const int sst = sel_stride(mD);
     for (int it = threadIdx.x; it < npos; it += blockDim.x) {
+        const int p = it < mD ? J.qb[D] + it : J.cqb[D] + (it - mD);
+        const uint4 *ps = T.pat_sel + 2 * (((D * kPatterns + p) << 1) + c - 1);
+        const uint4 sc = ps[0], so = ps[1];
         if (it < mD) {
-            const QInfo q = T.qinfo[J.qb[D] + it];
-            const unsigned mc = c == 1 ? q.bm : q.wm, mo = c == 1 ? q.wm : q.bm;
-            const uint4 sc = T.sel[D * 512 + mc], so = T.sel[D * 512 + mo];
             L.sel[it] = make_uint2(sc.x, so.x);
             L.sel[sst + it] = make_uint2(sc.y, so.y);
             L.sel[2 * sst + it] = make_uint2(sc.z, so.z);
             L.sel[3 * sst + it] = make_uint2(sc.w, so.w);
-            PosChild &r = L.pch[it];
-            unsigned empt = staged ? ~(unsigned)(q.bm | q.wm) & 0x1ffu : 0u;
-            int n = 0;
-            while (empt) {
-                const int cell = __builtin_ctz(empt);
-                empt &= empt - 1;
-                r.child[n++] = T.canon[q.code + c * c_pow3[cell]];
+            if (staged) {
+                L.pch[it] = T.pat_child[(p << 1) + c - 1];
+            } else {
+                L.pch[it].nchild = 0;
             }
-            r.nchild = (uint16_t)n;
         } else {
-            const QInfo q = T.qinfo[J.cqb[D] + (it - mD)];
-            const unsigned mc = c == 1 ? q.bm : q.wm, mo = c == 1 ? q.wm : q.bm;
             ChildPosRec &cr = L.cpos[it - mD];
-            cr.sel_c = T.sel[D * 512 + mc];
-            cr.sel_o = T.sel[D * 512 + mo];
+            cr.sel_c = sc;
+            cr.sel_o = so;
         }
     }
     __syncthreads();
@@ -448,9 +449,7 @@ __device__ __forceinline__ void sweep_tile(const SweepJob &J, const DevTables &T
     for (int it = threadIdx.x; it < nlines * 2 * 33; it += blockDim.x) {
         const int vx = (int)(((uint32_t)it * 1986u) >> 16), l = it - 33 * vx;
         const LineMasks *lmq = L.lmq + 4 * vx;
-        // chunk slots carry two references (0xffff: unused slot), the lines
-        // missing D three
-        const uint32_t refs = l < 18 ? (uint32_t)T.chunk_ref[D * 18 + l] | 0xff0000u : T.u_ref[D * 15 + (l - 18)];
+        const uint32_t refs = it == (int)threadIdx.x ? refs0 : item_refs(it);
         uint2 pr = ref_product3<D>(lmq, refs);
         if (l < 18) {
             if ((refs & 0xffffu) == 0xffffu) pr = make_uint2(0, 0);

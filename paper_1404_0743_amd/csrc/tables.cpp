@@ -245,6 +245,32 @@ static void build_symmetry(HostTables &t)
             }
 }
 
+static void build_pattern_lookups(HostTables &t)
+{
+    static const int pow3[9] = {1, 3, 9, 27, 81, 243, 729, 2187, 6561};
+    t.pat_lm.assign(4 * kPatterns * 2, LineMasks{0, 0, 0});
+    t.pat_sel.assign(4 * kPatterns * 2 * 2 * 4, 0);
+    t.pat_child.assign(kPatterns * 2, PosChild{});
+    for (int p = 0; p < kPatterns; p++) {
+        const QInfo &q = t.qinfo[p];
+        for (int x = 1; x <= 2; x++) {
+            const unsigned mine = x == 1 ? q.bm : q.wm, other = x == 1 ? q.wm : q.bm;
+            for (int j = 0; j < 4; j++) {
+                t.pat_lm[(j * kPatterns + p) * 2 + x - 1] = t.lm[j * 512 + mine];
+                uint32_t *ps = &t.pat_sel[((j * kPatterns + p) * 2 + x - 1) * 8];
+                for (int w = 0; w < 4; w++) {
+                    ps[w] = t.sel[(j * 512 + mine) * 4 + w];
+                    ps[4 + w] = t.sel[(j * 512 + other) * 4 + w];
+                }
+            }
+            PosChild &r = t.pat_child[p * 2 + x - 1];
+            r.nchild = 0;
+            for (int cell = 0; cell < 9; cell++)
+                if (!(((q.bm | q.wm) >> cell) & 1u)) r.child[r.nchild++] = t.canon[q.code + x * pow3[cell]];
+        }
+    }
+}
+
 static void build(HostTables &t)
 {
     const int NC = 19683;
@@ -290,6 +316,7 @@ static void build(HostTables &t)
     build_symmetry(t);
     build_line_masks(t);
     build_line_structure(t);
+    build_pattern_lookups(t);
 }
 
 const HostTables &host_tables()

@@ -20,6 +20,12 @@ struct QInfo {
     uint16_t pad;
 };
 
+// The children of a pattern when one side moves: per empty cell, in
+// increasing cell order, the canonical child (class index | turns << 12).
+struct alignas(4) PosChild {
+    uint16_t nchild, child[9];
+};
+
 struct HostTables {
     int class_start[10][10];
     int class_size[10][10];
@@ -62,6 +68,17 @@ struct HostTables {
     // u_ref[D * 15 + i]: the 15 lines that miss quadrant D, each as up to
     // three refs (byte per ref, 0xff = none).
     std::vector<uint32_t> u_ref;      // [4 * 15]
+
+    // Per-pattern lookups of the sweep's tile set-up, each one load instead of
+    // a chain (pattern record, then the table it indexes), for pattern p
+    // (qinfo order), quadrant j and side x / mover c (1 black, 2 white):
+    // pat_lm[(j * kPatterns + p) * 2 + x - 1] = lm[j * 512 + stones of x in p];
+    // pat_sel[((j * kPatterns + p) * 2 + c - 1) * 2 + 0 / 1] = sel entries
+    // (4 words each, k = 0..3) of the mover's / the other side's stones of p;
+    // pat_child[p * 2 + c - 1] = the children of p when c moves.
+    std::vector<LineMasks> pat_lm;     // [4 * kPatterns * 2]
+    std::vector<uint32_t> pat_sel;     // [4 * kPatterns * 2 * 2 * 4]
+    std::vector<PosChild> pat_child;   // [kPatterns * 2]
 };
 
 // Built once on first use (thread-safe).
