@@ -175,7 +175,8 @@ def layers(P, torch, stream, resident=None):
             "plain_ms": med_plain, "plain_positions_per_s": positions / (med_plain * 1e-3),
             "batched_graph_ms": med_graph, "batched_positions_per_s": positions / (med_graph * 1e-3),
             "batched_over_plain": med_plain / med_graph, "same_bytes": same,
-            "tiles": info["tiles"], "grid": info["grid"]}
+            "tiles": info["tiles"], "grid": info["grid"],
+            "counts": table_counts(P, torch, [o for _, _, o in jobs], stream)}
         log("layer %d: plain %.3f ms, batched %.3f ms" % (stones, med_plain, med_graph))
     out["resident_child_bytes"] = sum(t.numel() * 8 for t in cache.values())
     if resident is not None:
@@ -346,6 +347,26 @@ NAMES = ("endgame_4096", "endgame_2p20", "layers", "serving", "serving_resident"
          "deep", "serving_deep")
 
 
+def table_counts(P, torch, tables, stream, acc=None):
+    """The per-slice checksum of Section VII: wins, ties and losses over
+    every (entry, rotation) pair of the tables (each entry holds 256
+    rotations of one board), and the entries whose win set is not inside
+    their not-lose set (none in a solved table).  acc: a device tensor of 4
+    int64 to add to (stream-ordered), else the totals are returned."""
+    own = acc is None
+    if own:
+        acc = torch.zeros(4, dtype=torch.int64, device="cuda")
+    out = torch.empty(4, dtype=torch.int64, device="cuda")
+    for t in tables:
+        P.pentago_table_counts(t, out, stream)
+        acc += out
+    if not own:
+        return None
+    torch.cuda.synchronize()
+    w, ti, lo, bad = (int(x) for x in acc.cpu())
+    return {"win": w, "tie": ti, "loss": lo, "invalid_entries": bad}
+
+
 def slices(P, torch, stream):
     """Whole slices 35 and 34 over D4 representatives: every D4-minimal
     section of the slice, children read from the representatives of the
@@ -386,7 +407,8 @@ def slices(P, torch, stream):
             "graph_positions_per_s": pos / (t_graph * 1e-3),
             "graph_positions_all_images_per_s": cover / (t_graph * 1e-3),
             "graph_algorithmic_GB_s": alg / (t_graph * 1e-3) / 1e9,
-            "graph_over_per_section": t_plain / t_graph, "same_bytes": bool(same)}
+            "graph_over_per_section": t_plain / t_graph, "same_bytes": bool(same),
+            "counts": table_counts(P, torch, tables.values(), stream)}
         del keep
         if stones == 34:
             # a server holding only the representatives of both slices answers
@@ -417,13 +439,12 @@ def slices(P, torch, stream):
     # slice 33 (1,343 sections, 337.8 GB of tables: more than the GPU holds
     # next to slice 34) from the slice-34 representatives, streamed through
     # one 64 GB arena in batches; the time counts the batched launches only
-    # (HIP events around each), not the per-batch checksums of the sink
+    # (HIP events around each), not the per-batch counts of the sink
     evs = []
-    sums = []
-    w = torch.randint(-(1 << 62), 1 << 62, (8,), dtype=torch.int64, device="cuda")
+    acc33 = torch.zeros(4, dtype=torch.int64, device="cuda")
 
     def sink(tables):
-        sums.append(sum((t * w).sum() for t in tables.values()))
+        table_counts(P, torch, tables.values(), stream, acc33)
 
     t0 = time.perf_counter()
     nb = S.solve_slice_streamed(33, above, sink, stream=stream, events=evs)
@@ -443,7 +464,8 @@ def slices(P, torch, stream):
         "sections": len(secs), "entries": entries, "bytes_written": 64 * entries, "batches": nb,
         "arena_bytes": 64 << 30, "gpu_ms": gpu_ms, "wall_s": wall,
         "positions": pos, "positions_per_s": pos / (gpu_ms * 1e-3),
-        "algorithmic_GB_s": 64 * (entries + reads) / (gpu_ms * 1e-3) / 1e9}
+        "algorithmic_GB_s": 64 * (entries + reads) / (gpu_ms * 1e-3) / 1e9,
+        "counts": dict(zip(("win", "tie", "loss", "invalid_entries"), (int(x) for x in acc33.cpu())))}
     log("slice 33 streamed: %d batches, %.1f ms GPU, %.1f s wall" % (nb, gpu_ms, wall))
     del above
     torch.cuda.empty_cache()

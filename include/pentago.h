@@ -247,6 +247,29 @@ int pentago_plan_info(const pentago_sweep_plan *plan, long long *tiles, int *gri
 /* Waits for the plan's work, then releases it. */
 int pentago_plan_destroy(pentago_sweep_plan *plan);
 
+/* ---------------------------------------------------------------- checks */
+
+/* Counts over a solved table of n entries (Section VII checks every computed
+ * slice by its numbers of won, tied and lost positions): out[0] wins, out[1]
+ * ties, out[2] losses, each over every (entry, rotation g) pair, 256 per
+ * entry (value = win + notlose - 1), and out[3] the entries whose win set is
+ * not inside their not-lose set (no solved table has one).  table: device,
+ * n x 64 B; out: 4 uint64 in device memory, written stream-ordered on
+ * hip_stream.  EINVAL for a NULL out, or a NULL table with n > 0. */
+int pentago_table_counts(const pentago_superinfo *table, uint64_t n, uint64_t *out, void *hip_stream);
+
+/* 0 if every entry of table[0, n) has its win set inside its not-lose set,
+ * else EINVAL (pentago_last_error() gives the number of bad entries).
+ * Synchronises hip_stream. */
+int pentago_validate_table(const pentago_superinfo *table, uint64_t n, void *hip_stream);
+
+/* Debug-validate mode, off by default: while on, pentago_solve_section,
+ * pentago_solve_section_d4, pentago_solve_sections(_d4) and
+ * pentago_plan_create(_d4) first check every child table they are given as
+ * pentago_validate_table does, and fail with EINVAL, launching nothing, if
+ * one is not valid.  The checks synchronise the call's stream. */
+int pentago_set_validate(int on);
+
 /* ---------------------------------------------------------------- endgame */
 
 /* Exact superinfo of n arbitrary boards, each solved to the full board over
@@ -260,8 +283,9 @@ int pentago_plan_destroy(pentago_sweep_plan *plan);
  *           quadrant code >= 19683, counts that are not a valid position, or
  *           more than 10 empty cells); such a board's output is all zero.
  * Boards may have different numbers of empty cells: the library bins them on
- * the device (most empty cells first) and solves all of them in one
- * persistent launch fed by a device work queue.  ERANGE for n > 2^30. */
+ * the device (most empty cells first) and solves them in one persistent
+ * launch per class of empty cells (8-10, 7, up to 6), each fed by a device
+ * work queue.  ERANGE for n > 2^30. */
 int pentago_eval_batch(const pentago_board *boards, size_t n, pentago_superinfo *out,
                        int32_t *status, void *hip_stream);
 

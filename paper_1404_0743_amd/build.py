@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpentago.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["tables.cpp", "sweep.hip", "endgame.hip", "api.hip", "eval.hip", "debug.hip", "tune.hip", "batch.hip",
-           "serve.hip", "symmetry.hip", "deep.hip", "noalloc.hip", "terminal.hip"]
+           "serve.hip", "symmetry.hip", "deep.hip", "noalloc.hip", "terminal.hip", "check.hip"]
 HIPCC = "/opt/rocm/bin/hipcc"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -360,6 +360,8 @@ int pentago_solve_section(pentago_section s, const pentago_superinfo *const chil
     SweepJob J;
     rc = make_job(s, child, out, &J, -1, 0);
     if (rc) return rc;
+    rc = validate_children(J, (hipStream_t)hip_stream);
+    if (rc) return rc;
     return run_job(J, T, (hipStream_t)hip_stream);
 }
 

@@ -84,6 +84,8 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
             if (rc) return rc;
         }
         if (reps) set_child_syms(jobs[i].section, jobs[i].child, &J[i]);
+        rc = validate_children(J[i], stream);
+        if (rc) return rc;
     }
     // jobs whose tiles need more than kBatchLds even with one line (long
     // lines of large classes) go first and to their own launch, so that their

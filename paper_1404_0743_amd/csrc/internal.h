@@ -27,6 +27,9 @@ int make_job(const pentago_section &s, const pentago_superinfo *const child[4],
              int force_order = -1);
 size_t prep_bytes(const SweepJob &J, int j);
 int run_job(SweepJob &J, const DevTables &T, hipStream_t st);
+// With pentago_set_validate(1): EINVAL unless every child table J reads has
+// each entry's win set inside its not-lose set (synchronises st); else 0.
+int validate_children(const SweepJob &J, hipStream_t st);
 // Tile shape of a section geometry chosen by the autotuner (0 lines: none).
 struct TileShape {
     int lines;

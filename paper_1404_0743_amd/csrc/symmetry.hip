@@ -283,6 +283,8 @@ int pentago_solve_section_d4(pentago_section s, const pentago_superinfo *const r
     rc = make_job(s, rep, out, &J, -1, 0);
     if (rc) return rc;
     set_child_syms(s, rep, &J);
+    rc = validate_children(J, (hipStream_t)hip_stream);
+    if (rc) return rc;
     return run_job(J, T, (hipStream_t)hip_stream);
 }
 

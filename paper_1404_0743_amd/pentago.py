@@ -87,6 +87,9 @@ _SIGS = {
     "pentago_eval_batch_grouped": ([_P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
     "pentago_init": ([], ctypes.c_int),
     "pentago_autotune_eval": ([_P, ctypes.c_size_t, _P, _P, _P, _P], ctypes.c_int),
+    "pentago_table_counts": ([_P, ctypes.c_uint64, _P, _P], ctypes.c_int),
+    "pentago_validate_table": ([_P, ctypes.c_uint64, _P], ctypes.c_int),
+    "pentago_set_validate": ([ctypes.c_int], ctypes.c_int),
     "pentago_eval_batch_noalloc": ([_P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
     "pentago_serve_create": ([_P, _P], ctypes.c_int),
     "pentago_serve_add_section": ([_P, Section, _P], ctypes.c_int),
@@ -382,6 +385,26 @@ def pentago_autotune_eval(boards, out, stream=None):
     _check(lib().pentago_autotune_eval(_dev_ptr(boards), n, _dev_ptr(out), _stream(stream), th,
                                        ctypes.byref(ms)), "pentago_autotune_eval")
     return (th[0], th[1]), ms.value
+
+
+def pentago_table_counts(table, out, stream=None):
+    """out (device, 4 int64): wins, ties, losses over every (entry,
+    rotation) pair of the table, and its invalid entries (stream-ordered)."""
+    n = table.numel() * table.element_size() // 64
+    _check(lib().pentago_table_counts(_dev_ptr(table), n, _dev_ptr(out), _stream(stream)),
+           "pentago_table_counts")
+
+
+def pentago_validate_table(table, stream=None):
+    """Raises PentagoError (EINVAL) if an entry's win set is not inside its
+    not-lose set; synchronises the stream."""
+    n = table.numel() * table.element_size() // 64
+    _check(lib().pentago_validate_table(_dev_ptr(table), n, _stream(stream)), "pentago_validate_table")
+
+
+def pentago_set_validate(on):
+    """Debug-validate mode: the sweeps check their child tables first."""
+    _check(lib().pentago_set_validate(1 if on else 0), "pentago_set_validate")
 
 
 def pentago_init():
