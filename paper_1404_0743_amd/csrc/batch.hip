@@ -20,7 +20,7 @@ struct pentago_sweep_plan {
     int njobs = 0, nunits = 0;
     long long total_tiles = 0, total_chunks = 0;
     int lds_bytes = 0;
-    // jobs [0, nbig) have tiles above kBatchLds of LDS even with one line;
+    // jobs [0, nbig) have tiles above the LDS cap even with one line;
     // they take a second launch, beside the first on a side stream
     int nbig = 0;
     long long tiles_big = 0;
@@ -42,19 +42,34 @@ namespace pg {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// LDS bound of one batched tile (bytes): three workgroups per CU, the
+// LDS bound of one batched tile (bytes) unless pentago_autotune_sections
+// has picked one for the layer's stone count: three workgroups per CU, the
 // headline tile shape (7 lines of 160 patterns) included.
 constexpr int kBatchLds = 53248;
+// Caps the autotuner tries (the kernel runs at most three 512-thread
+// workgroups per CU, so larger caps only cost occupancy).
+constexpr int kBatchCaps[] = {24576, 32768, 40960, 53248};
+
+static std::mutex g_cap_mutex;
+static int g_cap[37];   // per stone count; 0: kBatchLds
+
+static int batch_cap(int stones)
+{
+    std::lock_guard<std::mutex> lock(g_cap_mutex);
+    const int c = stones >= 0 && stones <= 36 ? g_cap[stones] : 0;
+    return c > 0 ? c : kBatchLds;
+}
 
 // Build a plan: job table in decreasing order of work, prep units for the
 // dimensions that are not staged, and the device block holding all of it.
 // With `stream` the device block is allocated stream-ordered on it.
 static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t stream, bool async,
-                      bool reps, pentago_sweep_plan **out)
+                      bool reps, pentago_sweep_plan **out, int cap = 0)
 {
     if (!jobs || n == 0) return fail(PENTAGO_EINVAL, "no jobs");
     if (n > 65536) return fail(PENTAGO_ERANGE, "more than 65536 jobs");
     const int stones = section_stones(jobs[0].section);
+    const int lds_cap = cap > 0 ? cap : batch_cap(stones);
     std::vector<SweepJob> J(n);
     for (size_t i = 0; i < n; i++) {
         if (section_stones(jobs[i].section) != stones)
@@ -75,11 +90,11 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
             if (rc) return rc;
         }
         // a launch's occupancy follows its largest tile's LDS: keep every
-        // tile within kBatchLds by taking fewer lines per tile
-        if (J[i].lds_bytes > kBatchLds && J[i].G > 1) {
+        // tile within the cap by taking fewer lines per tile
+        if (J[i].lds_bytes > lds_cap && J[i].G > 1) {
             int G = J[i].G;
             const int cmd = (J[i].emask >> J[i].d) & 1 ? J[i].cm[J[i].d] : 0;
-            while (G > 1 && sweep_lds_bytes(G, J[i].m[J[i].d], cmd) > kBatchLds) G--;
+            while (G > 1 && sweep_lds_bytes(G, J[i].m[J[i].d], cmd) > lds_cap) G--;
             rc = make_job(jobs[i].section, jobs[i].child, jobs[i].out, &J[i], J[i].d, G);
             if (rc) return rc;
         }
@@ -87,7 +102,7 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
         rc = validate_children(J[i], stream);
         if (rc) return rc;
     }
-    // jobs whose tiles need more than kBatchLds even with one line (long
+    // jobs whose tiles need more than the cap even with one line (long
     // lines of large classes) go first and to their own launch, so that their
     // LDS does not set the occupancy of every other tile; within each group,
     // largest sections first: their tiles start early and small ones fill the
@@ -95,7 +110,7 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
     std::vector<size_t> order(n);
     std::iota(order.begin(), order.end(), 0);
     auto work = [&](size_t i) { return (double)J[i].m[0] * J[i].m[1] * J[i].m[2] * J[i].m[3]; };
-    auto big = [&](size_t i) { return J[i].lds_bytes > kBatchLds; };
+    auto big = [&](size_t i) { return J[i].lds_bytes > lds_cap; };
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
         if (big(a) != big(b)) return big(a);
         return work(a) > work(b);
@@ -321,6 +336,53 @@ int pentago_solve_sections(const pentago_section_job *jobs, size_t n, void *hip_
 int pentago_solve_sections_d4(const pentago_section_job *jobs, size_t n, void *hip_stream)
 {
     return solve_sections(jobs, n, hip_stream, true);
+}
+
+int pentago_autotune_sections(const pentago_section_job *jobs, size_t n, int reps, void *hip_stream,
+                              int *cap_bytes, float *best_ms)
+{
+    if (!jobs || n == 0) return fail(PENTAGO_EINVAL, "no jobs");
+    const hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return fail(PENTAGO_EDEVICE, "hipEventCreate");
+    int best_cap = 0, rc = 0;
+    float best = 1e30f;
+    for (int cap : kBatchCaps) {
+        pentago_sweep_plan *P = nullptr;
+        rc = plan_build(jobs, n, st, true, reps != 0, &P, cap);
+        if (rc) break;
+        rc = plan_enqueue(P, st);  // warm-up
+        float t = 1e30f;
+        for (int r = 0; r < 3 && rc == 0; r++) {
+            (void)hipEventRecord(a, st);
+            rc = plan_enqueue(P, st);
+            (void)hipEventRecord(b, st);
+            if (rc == 0 && hipEventSynchronize(b) != hipSuccess) rc = fail(PENTAGO_EDEVICE, "hipEventSynchronize");
+            float ms = 0;
+            if (rc == 0) (void)hipEventElapsedTime(&ms, a, b);
+            t = std::min(t, ms);
+        }
+        (void)hipFreeAsync(P->dev, st);
+        (void)hipStreamSynchronize(st);
+        delete P;
+        if (rc) break;
+        if (t < best) {
+            best = t;
+            best_cap = cap;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return rc;
+    const int stones = section_stones(jobs[0].section);
+    {
+        std::lock_guard<std::mutex> lock(g_cap_mutex);
+        if (stones >= 0 && stones <= 36) g_cap[stones] = best_cap;
+    }
+    if (cap_bytes) *cap_bytes = best_cap;
+    if (best_ms) *best_ms = best;
+    return 0;
 }
 
 }  // extern "C"

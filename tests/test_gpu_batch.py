@@ -117,6 +117,26 @@ def test_autotuned_tiles_give_same_bytes(P):
     assert torch.equal(ref, out2)
 
 
+@pytest.mark.parametrize("stones", [34, 33])
+def test_autotuned_batch_cap_gives_same_bytes(P, stones):
+    """The batched sweep's LDS-cap autotuner leaves the jobs' results in
+    their outputs, and later batches of that stone count (which take the
+    tuned cap) give the same bytes as the per-section sweep."""
+    log("batch autotune", stones)
+    secs, plain, jobs = layer(P, stones, 16, seed=700 + stones)
+    cap, ms = P.pentago_autotune_sections(jobs)
+    assert cap in (24576, 32768, 40960, 53248) and ms > 0
+    torch.cuda.synchronize()
+    for s, ref, (_, _, out) in zip(secs, plain, jobs):
+        assert torch.equal(ref, out), s
+    for _, _, out in jobs:
+        out.fill_(-1)
+    P.pentago_solve_sections(jobs)
+    torch.cuda.synchronize()
+    for s, ref, (_, _, out) in zip(secs, plain, jobs):
+        assert torch.equal(ref, out), s
+
+
 # sections whose staged quadrant (the one with most empty cells) is 2, 1, 0
 # and 3, with full-board children (35 stones) or children from the chain
 SHAPE_SECTIONS = [((7, 2), (2, 7), (1, 7), (8, 1)),
