@@ -247,22 +247,28 @@ __device__ __forceinline__ Set256 load_rotated(const uint32_t *p, int k)
 // internal layout (64 B each, in the child section's blocked order).
 template <int D, int JD>
 __device__ __forceinline__ void direct_children(const SweepJob &J, const DevTables &T,
-                                                const Idx4 &idx, const QInfo &q, Set256 &Wnt,
-                                                Set256 &Nnt)
+                                                const Idx4 &idx, Set256 &Wnt, Set256 &Nnt)
 {
     int cshape[4] = {J.m[0], J.m[1], J.m[2], J.m[3]};
     cshape[JD] = J.cm[JD];
     constexpr int ip = JD == 3 ? D : JD;
-    unsigned empt = ~(unsigned)(q.bm | q.wm) & 0x1ffu;
-    while (empt) {
-        const int cell = __builtin_ctz(empt);
-        empt &= empt - 1;
-        const uint16_t cc = T.canon[q.code + J.mover * c_pow3[cell]];
-        Idx4 cidx = idx;
-        cidx.v[JD] = cc & 0xfff;
-        const uint4 *p = J.prep[JD] + 4 * block_offset(cshape, cidx.v);
-        s_or_into(Wnt, shift_dim(set_from(p), ip, cc >> 12));
-        s_or_into(Nnt, shift_dim(set_from(p + 2), ip, cc >> 12));
+    // the parent's pattern along JD and its children: five words, one load
+    // each (word 0: count | child 0 << 16, word i: children 2i - 1, 2i)
+    const uint32_t *pw = (const uint32_t *)(T.pat_child + ((J.qb[JD] + idx.v[JD]) << 1) + J.mover - 1);
+    uint32_t w[5];
+#pragma unroll
+    for (int i = 0; i < 5; i++) w[i] = pw[i];
+    const int n = (int)(w[0] & 0xffffu);
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        if (k < n) {
+            const uint32_t cc = (w[(k + 1) >> 1] >> (16 * ((k + 1) & 1))) & 0xffffu;
+            Idx4 cidx = idx;
+            cidx.v[JD] = cc & 0xfff;
+            const uint4 *p = J.prep[JD] + 4 * block_offset(cshape, cidx.v);
+            s_or_into(Wnt, shift_dim(set_from(p), ip, cc >> 12));
+            s_or_into(Nnt, shift_dim(set_from(p + 2), ip, cc >> 12));
+        }
     }
 }
 
@@ -593,13 +599,10 @@ __device__ __forceinline__ void sweep_tile(const SweepJob &J, const DevTables &T
         }
         // Children along the other dimensions with empty cells.
         if (J.emask & ~(1 << D)) {
-            QInfo qi[4];
-#pragma unroll
-            for (int j = 0; j < 4; j++) qi[j] = T.qinfo[J.qb[j] + idx.v[j]];
-            if (D != 0 && (J.emask & 1)) direct_children<D, 0>(J, T, idx, qi[0], Wnt, Nnt);
-            if (D != 1 && (J.emask & 2)) direct_children<D, 1>(J, T, idx, qi[1], Wnt, Nnt);
-            if (D != 2 && (J.emask & 4)) direct_children<D, 2>(J, T, idx, qi[2], Wnt, Nnt);
-            if (D != 3 && (J.emask & 8)) direct_children<D, 3>(J, T, idx, qi[3], Wnt, Nnt);
+            if (D != 0 && (J.emask & 1)) direct_children<D, 0>(J, T, idx, Wnt, Nnt);
+            if (D != 1 && (J.emask & 2)) direct_children<D, 1>(J, T, idx, Wnt, Nnt);
+            if (D != 2 && (J.emask & 4)) direct_children<D, 2>(J, T, idx, Wnt, Nnt);
+            if (D != 3 && (J.emask & 8)) direct_children<D, 3>(J, T, idx, Wnt, Nnt);
         }
         const uint2 *lut = L.lut + kLutStride * v;
         const uint2 s0 = L.sel[iD], s1 = L.sel[sst + iD], s2 = L.sel[2 * sst + iD], s3 = L.sel[3 * sst + iD];
