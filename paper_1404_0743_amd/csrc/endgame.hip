@@ -84,7 +84,10 @@ template <int GROUP>
 __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, uint4 *buf1,
                            uint4 *ftab, uint4 *out, int *s_slot_q, int *s_slot_l)
 {
-    const int lane = GROUP >= 256 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+    // GROUP < 64: a part of a wave; the other parts of the wave solve roots
+    // with as many empty cells, so that every wave barrier below is reached
+    // by all of them together
+    const int lane = GROUP >= 256 ? (int)threadIdx.x : (int)(threadIdx.x & (GROUP - 1));
     if (lane == 0) {
         int n = 0;
         for (int j = 0; j < 4; j++) {
@@ -264,8 +267,10 @@ __global__ void zero_ints_kernel(int *p, int n)
 //            first `slots` workgroups own a slot: they take the 9-10 queue
 //            first, then join the others on the 8-empty queue);
 //   class 1: 7 empty cells, a workgroup per root, a smaller LDS footprint;
-//   class 2: up to kWaveMaxEmpties, one wave per root, four per workgroup,
-//            synchronised per wave only.
+//   class 2: up to kWaveMaxEmpties, synchronised per wave only: a wave
+//            solves four roots with up to 4 empty cells at once (16 lanes
+//            each), two with 5 (32 lanes), one with 6, each on its own part
+//            of the wave's LDS.
 constexpr int kWaveMaxEmpties = 6;
 // two layers of the widest 6-empty layer, then the five-set tables (C(6,3) = 20)
 constexpr int kWaveLdsBytes = 2 * 90 * 64 + 2 * 20 * 32;
@@ -281,7 +286,7 @@ __global__ void __launch_bounds__(NT)
     // bins are ordered by empty cells, most first: e occupies [start[e], start[e - 1])
     const int lo = CLS == 0 ? 0 : CLS == 1 ? start[7] : start[kWaveMaxEmpties];
     const int hi = CLS == 0 ? start[7] : CLS == 1 ? start[kWaveMaxEmpties] : start[11];
-    if (CLS < 2) {
+    if constexpr (CLS < 2) {
         // class 0: roots with 9 or 10 empty cells, [0, big), come from queue 3
         // and only go to workgroups that own a global layer slot; the rest of
         // the class, [big, hi), from queue 0.  Class 1 uses queue 1 only.
@@ -314,17 +319,49 @@ __global__ void __launch_bounds__(NT)
             __syncthreads();
         }
     } else {
-        const int w = threadIdx.x >> 6;
+        // A wave takes a chunk of K roots of one bin (K = 4 up to 4 empty
+        // cells, 2 for 5, 1 for 6: the widest layers have 12, 30 and 90
+        // nodes); the roots of a chunk have the same layers, so the wave
+        // synchronises them together.  Chunks are numbered bin by bin, most
+        // empty cells first; the last chunk of a bin repeats the bin's last
+        // root where it runs short (the copy writes the same bytes).
+        __shared__ int s_sub[4][4][2][10];
+        (void)lo;
+        (void)hi;
+        const int w = threadIdx.x >> 6, wl = threadIdx.x & 63;
         uint4 *wb = lds + (size_t)w * (kWaveLdsBytes / 16);
         for (;;) {
             unsigned long long got = 0;
-            if ((threadIdx.x & 63) == 0) got = atomicAdd(&counter[2], 1ull);
-            const long long item = lo + (long long)__shfl(got, 0, 64);
-            if (item >= hi) break;
-            const int root = order[item];
+            if (wl == 0) got = atomicAdd(&counter[2], 1ull);
+            const long long c = (long long)__shfl(got, 0, 64);
+            int e = -1, K = 1, base = 0, last = 0;
+            long long cum = 0;
+            for (int b = kWaveMaxEmpties; b >= 0; b--) {
+                const int blo = start[b], bhi = b == 0 ? start[11] : start[b - 1];
+                const int kb = b <= 4 ? 4 : b == 5 ? 2 : 1;
+                const long long nch = (bhi - blo + kb - 1) / kb;
+                if (e < 0 && c < cum + nch) {
+                    e = b;
+                    K = kb;
+                    base = blo + (int)(c - cum) * kb;
+                    last = bhi - 1;
+                }
+                cum += nch;
+            }
+            if (e < 0) break;
+            const int g = wl / (64 / K);
+            const int root = order[min(base + g, last)];
             const RootInfo R = decode_root(boards[root]);
-            solve_root<64>(R, T, wb, wb + 4 * 90, wb + 8 * 90, out + 4 * (size_t)root, s_slots[w][0],
-                           s_slots[w][1]);
+            uint4 *o = out + 4 * (size_t)root;
+            if (K == 4) {
+                uint4 *sb = wb + g * 200;   // 3.2 KB each: layers of 12 nodes, tables of 6 subsets
+                solve_root<16>(R, T, sb, sb + 4 * 12, sb + 8 * 12, o, s_sub[w][g][0], s_sub[w][g][1]);
+            } else if (K == 2) {
+                uint4 *sb = wb + g * 400;   // 6.4 KB each: layers of 30 nodes, tables of 10 subsets
+                solve_root<32>(R, T, sb, sb + 4 * 30, sb + 8 * 30, o, s_sub[w][g][0], s_sub[w][g][1]);
+            } else {
+                solve_root<64>(R, T, wb, wb + 4 * 90, wb + 8 * 90, o, s_sub[w][0][0], s_sub[w][0][1]);
+            }
             wave_sync();
         }
     }
