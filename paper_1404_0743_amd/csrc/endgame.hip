@@ -15,9 +15,11 @@ namespace pg {
 // B = F_parent(node) | rmax(not W) (64 B) in a layer buffer.
 // ---------------------------------------------------------------------------
 
-// Per root: two layers of node records (64 B each), then the layer's
-// five-set tables (two colours x the largest C(e, s) subsets, 32 B each).
-int dag_ftab_bytes(int e) { return 2 * dag_layout(e).max_subsets * 32; }
+// A root solved by a workgroup: two layers of node records (64 B each), then
+// three five-set tables (the largest C(e, s) subsets, 32 B each): the two
+// colours' tables of the current layer and, with 512 threads or more, the
+// next layer's, computed while the current layer's nodes read the other two.
+int dag_ftab_bytes(int e) { return 3 * dag_layout(e).max_subsets * 32; }
 
 int dag_lds_bytes(int e)
 {
@@ -69,25 +71,62 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Five-set of one board: the colour's stones xm0 plus the empty cells of
+// subset m, stored as table entry r.  PL: the table is two planes of `smax`
+// uint4 (entry r's halves at r and smax + r), else entries of two uint4.
+template <bool PL>
+__device__ __forceinline__ void five_entry(const DevTables &T, const unsigned xm0[4], unsigned m, int e,
+                                           const int *s_slot_q, const int *s_slot_l, uint4 *tab, int smax,
+                                           int r)
+{
+    unsigned xm[4] = {xm0[0], xm0[1], xm0[2], xm0[3]};
+    for (int sl = 0; sl < e; sl++)
+        if ((m >> sl) & 1) {
+            const int q = s_slot_q[sl];
+            const unsigned bit = 1u << s_slot_l[sl];
+            xm[0] |= q == 0 ? bit : 0u;
+            xm[1] |= q == 1 ? bit : 0u;
+            xm[2] |= q == 2 ? bit : 0u;
+            xm[3] |= q == 3 ? bit : 0u;
+        }
+    const Set256 F = board_five(T, xm);
+    tab[PL ? r : 2 * r] = make_uint4(F.w[0], F.w[1], F.w[2], F.w[3]);
+    tab[PL ? smax + r : 2 * r + 1] = make_uint4(F.w[4], F.w[5], F.w[6], F.w[7]);
+}
+
 // Solve one root with a group of GROUP threads: the whole workgroup (256 or
-// 512) or one wave (64).  `buf0` and `buf1` hold two layers of A/B records (64 B per
-// node); `ftab` the five-set tables of the current layer; slot_q/slot_l (10
-// ints each, LDS) the root's empty cells.
+// 512) or a wave or part of one (64, 32, 16).  `buf0` and `buf1` hold
+// two layers of A/B records, room for `cap` nodes each; `ftab` the five-set
+// tables (three with 512 threads or more, else two); slot_q/slot_l (10 ints
+// each, LDS) the root's empty cells.
 //
 // Five-sets: the nodes of layer t hold ceil(t/2) stones of the root's mover
 // and floor(t/2) of the other side in the root's empty cells, and a colour's
-// five-set depends only on which cells hold that colour.  So each layer first
-// computes the five-set of every subset of the empty cells of those two sizes
-// (C(e, s) boards per colour instead of one per node and colour: 581 boards
-// against 4246 for 8 empty cells), and each node reads its two.
+// five-set depends only on which cells hold that colour.  So the five-set of
+// every subset of the empty cells of those two sizes is tabled (C(e, s)
+// boards per colour instead of one per node and colour), and each node reads
+// its two.  From layer t to t - 1 one size stays (the mover's when t is
+// even, the other side's when t is odd), so each layer tables one colour
+// only: after the layer, over the table it replaces, or, with 512 threads or
+// more, in the same pass as the layer's nodes, on the lanes the nodes leave
+// free (a layer of 8 empty cells has up to 560 nodes, so the second pass of
+// 512 lanes is mostly free), into the third table.
+//
+// Layouts: with 512 threads or more, records and tables are planes (node
+// i's words 0-3 of A, 4-7 of A, 0-3 of B, 4-7 of B at [k * cap + i], so
+// consecutive nodes take consecutive 16-byte slots); below, a node's record
+// is four consecutive uint4 (measured: the planes' extra address arithmetic
+// costs the smaller groups more than their LDS accesses gain).
 template <int GROUP>
-__device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, uint4 *buf1,
+__device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, uint4 *buf1, int cap,
                            uint4 *ftab, uint4 *out, int *s_slot_q, int *s_slot_l)
 {
+    constexpr bool WG = GROUP >= 256;
+    constexpr bool WIDE = GROUP >= 512;
     // GROUP < 64: a part of a wave; the other parts of the wave solve roots
     // with as many empty cells, so that every wave barrier below is reached
     // by all of them together
-    const int lane = GROUP >= 256 ? (int)threadIdx.x : (int)(threadIdx.x & (GROUP - 1));
+    const int lane = WG ? (int)threadIdx.x : (int)(threadIdx.x & (GROUP - 1));
     if (lane == 0) {
         int n = 0;
         for (int j = 0; j < 4; j++) {
@@ -100,14 +139,18 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
                 }
         }
     }
-    if (GROUP >= 256) __syncthreads();
+    if (WG) __syncthreads();
     else wave_sync();
     const int e = R.e;
     static_assert(kDagEdgeWords == 16, "edge records are two uint4");
     const uint4 *edges = T.dag_edge + 2 * T.dag_node_off[e];
     const uint16_t *smask = T.dag_sub_mask + T.dag_sub_off[e];
     const int *layer = T.dag_layer[e];
+    const int *sstart = T.dag_sub_start[e];
     const int smax = T.dag_sub_max[e];
+    // record piece j of node i, table half h of entry r
+    const int rs = WIDE ? cap : 1, rn = WIDE ? 1 : 4;
+    const int fs = WIDE ? smax : 1, fn = WIDE ? 1 : 2;
     // the root mover's stones and the other side's, per quadrant
     unsigned cm0[4], om0[4];
 #pragma unroll
@@ -115,46 +158,53 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
         cm0[j] = R.mover == 1 ? R.bm[j] : R.wm[j];
         om0[j] = R.mover == 1 ? R.wm[j] : R.bm[j];
     }
-    uint4 *cur = buf0, *prev = buf1;
-    for (int t = e; t >= 0; t--) {
-        const int n0 = layer[t], n1 = layer[t + 1];
-        const int x = (t & 1) ? 3 - R.mover : R.mover;   // side to move at layer t
-        // five-set tables of the layer: entries [0, nc) for the root mover's
-        // subsets of size ceil(t/2), [smax, smax + no) for the other side's
-        const int sc = (t + 1) >> 1, so = t >> 1;
-        const int nc = T.dag_sub_start[e][sc + 1] - T.dag_sub_start[e][sc];
-        const int no = T.dag_sub_start[e][so + 1] - T.dag_sub_start[e][so];
+    // tables (2 * smax uint4 each): the root mover's subsets of the current
+    // layer's size, the other side's, and (WIDE) the free one
+    int tc = 0, to = 1, tf = 2;
+    {
+        const int sc = (e + 1) >> 1, so = e >> 1;
+        const int nc = sstart[sc + 1] - sstart[sc], no = sstart[so + 1] - sstart[so];
         for (int i = lane; i < nc + no; i += GROUP) {
             const bool mine = i < nc;
             const int r = mine ? i : i - nc;
-            const unsigned m = smask[T.dag_sub_start[e][mine ? sc : so] + r];
-            unsigned xm[4] = {mine ? cm0[0] : om0[0], mine ? cm0[1] : om0[1], mine ? cm0[2] : om0[2],
-                              mine ? cm0[3] : om0[3]};
-            for (int sl = 0; sl < e; sl++)
-                if ((m >> sl) & 1) {
-                    const int q = s_slot_q[sl];
-                    const unsigned bit = 1u << s_slot_l[sl];
-                    xm[0] |= q == 0 ? bit : 0u;
-                    xm[1] |= q == 1 ? bit : 0u;
-                    xm[2] |= q == 2 ? bit : 0u;
-                    xm[3] |= q == 3 ? bit : 0u;
-                }
-            const Set256 F = board_five(T, xm);
-            uint4 *dst = ftab + 2 * ((mine ? 0 : smax) + r);
-            dst[0] = make_uint4(F.w[0], F.w[1], F.w[2], F.w[3]);
-            dst[1] = make_uint4(F.w[4], F.w[5], F.w[6], F.w[7]);
+            five_entry<WIDE>(T, mine ? cm0 : om0, smask[sstart[mine ? sc : so] + r], e, s_slot_q, s_slot_l,
+                             ftab + 2 * smax * (mine ? tc : to), smax, r);
         }
-        if (GROUP >= 256) __syncthreads();
-        else wave_sync();
+    }
+    if (WG) __syncthreads();
+    else wave_sync();
+    uint4 *cur = buf0, *prev = buf1;
+    for (int t = e; t >= 0; t--) {
+        const int n0 = layer[t], nodes = layer[t + 1] - n0;
+        const int x = (t & 1) ? 3 - R.mover : R.mover;   // side to move at layer t
+        // the table that changes for layer t - 1: the mover's when t is odd
+        const bool nmine = (t & 1) != 0;
+        const int nsize = nmine ? t >> 1 : (t - 1) >> 1;
+        const int nnext = t == 0 ? 0 : sstart[nsize + 1] - sstart[nsize];
+        const uint4 *fc = ftab + 2 * smax * tc, *fo = ftab + 2 * smax * to;
         // the layer's nodes: each node's edge record (two 16-byte loads,
         // independent of one another) holds its five-set table entries and
         // the index of the child on each free slot; e - t children per node
         const int nfree = e - t;
-        for (int i = n0 + lane; i < n1; i += GROUP) {
+        for (int k = lane; k < nodes + (WIDE ? nnext : 0); k += GROUP) {
+            if (WIDE && k >= nodes) {
+                const int r = k - nodes;
+                five_entry<WIDE>(T, nmine ? cm0 : om0, smask[sstart[nsize] + r], e, s_slot_q, s_slot_l,
+                                 ftab + 2 * smax * tf, smax, r);
+                continue;
+            }
+            const int i = n0 + k;
             const uint4 ra = edges[2 * i], rb = edges[2 * i + 1];
             const uint32_t w[8] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w};
-            const Set256 Fc = set_from(ftab + 2 * (w[0] & 0xffffu));
-            const Set256 Fo = set_from(ftab + 2 * (smax + (w[0] >> 16)));
+            const uint32_t ic = w[0] & 0xffffu, io = w[0] >> 16;
+            Set256 Fc, Fo;
+            {
+                const uint4 c0 = fc[fn * ic], c1 = fc[fn * ic + fs], o0 = fo[fn * io], o1 = fo[fn * io + fs];
+                Fc.w[0] = c0.x; Fc.w[1] = c0.y; Fc.w[2] = c0.z; Fc.w[3] = c0.w;
+                Fc.w[4] = c1.x; Fc.w[5] = c1.y; Fc.w[6] = c1.z; Fc.w[7] = c1.w;
+                Fo.w[0] = o0.x; Fo.w[1] = o0.y; Fo.w[2] = o0.z; Fo.w[3] = o0.w;
+                Fo.w[4] = o1.x; Fo.w[5] = o1.y; Fo.w[6] = o1.z; Fo.w[7] = o1.w;
+            }
             const Set256 &Fx = x == R.mover ? Fc : Fo;
             const Set256 &Fy = x == R.mover ? Fo : Fc;
             Set256 Wnt = s_zero(), Nnt = s_zero();
@@ -165,9 +215,12 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
                 for (int j = 0; j < 10; j++) {
                     if (j < nfree) {
                         const uint32_t ci = (w[1 + (j >> 1)] >> (16 * (j & 1))) & 0xffffu;
-                        const uint4 *p = prev + 4 * ci;
-                        s_or_into(Wnt, set_from(p));
-                        s_or_into(Nnt, set_from(p + 2));
+                        const uint4 *p = prev + rn * ci;
+                        const uint4 a0 = p[0], a1 = p[rs], b0 = p[2 * rs], b1 = p[3 * rs];
+                        Wnt.w[0] |= a0.x; Wnt.w[1] |= a0.y; Wnt.w[2] |= a0.z; Wnt.w[3] |= a0.w;
+                        Wnt.w[4] |= a1.x; Wnt.w[5] |= a1.y; Wnt.w[6] |= a1.z; Wnt.w[7] |= a1.w;
+                        Nnt.w[0] |= b0.x; Nnt.w[1] |= b0.y; Nnt.w[2] |= b0.z; Nnt.w[3] |= b0.w;
+                        Nnt.w[4] |= b1.x; Nnt.w[5] |= b1.y; Nnt.w[6] |= b1.z; Nnt.w[7] |= b1.w;
                     }
                 }
             }
@@ -178,15 +231,29 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
             } else {
                 Set256 A, B;
                 child_terms(Fy, W, N, A, B);
-                uint4 *p = cur + 4 * (i - n0);
+                uint4 *p = cur + rn * k;
                 p[0] = make_uint4(A.w[0], A.w[1], A.w[2], A.w[3]);
-                p[1] = make_uint4(A.w[4], A.w[5], A.w[6], A.w[7]);
-                p[2] = make_uint4(B.w[0], B.w[1], B.w[2], B.w[3]);
-                p[3] = make_uint4(B.w[4], B.w[5], B.w[6], B.w[7]);
+                p[rs] = make_uint4(A.w[4], A.w[5], A.w[6], A.w[7]);
+                p[2 * rs] = make_uint4(B.w[0], B.w[1], B.w[2], B.w[3]);
+                p[3 * rs] = make_uint4(B.w[4], B.w[5], B.w[6], B.w[7]);
             }
         }
-        if (GROUP >= 256) __syncthreads();
+        if (WG) __syncthreads();
         else wave_sync();
+        if (WIDE) {
+            // the third table now holds the changing colour's; the old one is free
+            const int old = nmine ? tc : to;
+            if (nmine) tc = tf;
+            else to = tf;
+            tf = old;
+        } else if (nnext > 0) {
+            // the changing table, over the one it replaces
+            for (int r = lane; r < nnext; r += GROUP)
+                five_entry<WIDE>(T, nmine ? cm0 : om0, smask[sstart[nsize] + r], e, s_slot_q, s_slot_l,
+                                 ftab + 2 * smax * (nmine ? tc : to), smax, r);
+            if (WG) __syncthreads();
+            else wave_sync();
+        }
         uint4 *tmp = cur;
         cur = prev;
         prev = tmp;
@@ -301,7 +368,7 @@ __global__ void __launch_bounds__(NT)
                 if (item >= big) break;
                 const int root = order[item];
                 const RootInfo R = decode_root(boards[root]);
-                solve_root<NT>(R, T, mine, mine + 4 * kDagGlobalLayer, lds, out + 4 * (size_t)root,
+                solve_root<NT>(R, T, mine, mine + 4 * kDagGlobalLayer, kDagGlobalLayer, lds, out + 4 * (size_t)root,
                                 s_slots[0][0], s_slots[0][1]);
                 __syncthreads();
             }
@@ -314,7 +381,7 @@ __global__ void __launch_bounds__(NT)
             if (item >= hi) break;
             const int root = order[item];
             const RootInfo R = decode_root(boards[root]);
-            solve_root<NT>(R, T, lds, lds + 4 * T.dag_max[R.e], lds + 8 * T.dag_max[R.e],
+            solve_root<NT>(R, T, lds, lds + 4 * T.dag_max[R.e], T.dag_max[R.e], lds + 8 * T.dag_max[R.e],
                             out + 4 * (size_t)root, s_slots[0][0], s_slots[0][1]);
             __syncthreads();
         }
@@ -355,12 +422,12 @@ __global__ void __launch_bounds__(NT)
             uint4 *o = out + 4 * (size_t)root;
             if (K == 4) {
                 uint4 *sb = wb + g * 200;   // 3.2 KB each: layers of 12 nodes, tables of 6 subsets
-                solve_root<16>(R, T, sb, sb + 4 * 12, sb + 8 * 12, o, s_sub[w][g][0], s_sub[w][g][1]);
+                solve_root<16>(R, T, sb, sb + 4 * 12, 12, sb + 8 * 12, o, s_sub[w][g][0], s_sub[w][g][1]);
             } else if (K == 2) {
                 uint4 *sb = wb + g * 400;   // 6.4 KB each: layers of 30 nodes, tables of 10 subsets
-                solve_root<32>(R, T, sb, sb + 4 * 30, sb + 8 * 30, o, s_sub[w][g][0], s_sub[w][g][1]);
+                solve_root<32>(R, T, sb, sb + 4 * 30, 30, sb + 8 * 30, o, s_sub[w][g][0], s_sub[w][g][1]);
             } else {
-                solve_root<64>(R, T, wb, wb + 4 * 90, wb + 8 * 90, o, s_sub[w][0][0], s_sub[w][0][1]);
+                solve_root<64>(R, T, wb, wb + 4 * 90, 90, wb + 8 * 90, o, s_sub[w][0][0], s_sub[w][0][1]);
             }
             wave_sync();
         }
@@ -391,10 +458,10 @@ __global__ void __launch_bounds__(256)
             if (!ok) {
                 if (threadIdx.x < 4) out[4 * item + threadIdx.x] = make_uint4(0, 0, 0, 0);
             } else if (CLS == 0 && R.e > 8) {
-                solve_root<256>(R, T, mine, mine + 4 * kDagGlobalLayer, lds, out + 4 * (size_t)item,
+                solve_root<256>(R, T, mine, mine + 4 * kDagGlobalLayer, kDagGlobalLayer, lds, out + 4 * (size_t)item,
                                 s_slots[0][0], s_slots[0][1]);
             } else {
-                solve_root<256>(R, T, lds, lds + 4 * T.dag_max[R.e], lds + 8 * T.dag_max[R.e],
+                solve_root<256>(R, T, lds, lds + 4 * T.dag_max[R.e], T.dag_max[R.e], lds + 8 * T.dag_max[R.e],
                                 out + 4 * (size_t)item, s_slots[0][0], s_slots[0][1]);
             }
             __syncthreads();
@@ -411,7 +478,7 @@ __global__ void __launch_bounds__(256)
             if (!R.valid || R.e > kWaveMaxEmpties) {
                 if ((threadIdx.x & 63) < 4) out[4 * item + (threadIdx.x & 3)] = make_uint4(0, 0, 0, 0);
             } else {
-                solve_root<64>(R, T, wb, wb + 4 * 90, wb + 8 * 90, out + 4 * (size_t)item, s_slots[w][0],
+                solve_root<64>(R, T, wb, wb + 4 * 90, 90, wb + 8 * 90, out + 4 * (size_t)item, s_slots[w][0],
                                s_slots[w][1]);
             }
             wave_sync();
@@ -432,10 +499,10 @@ __global__ void __launch_bounds__(256)
         const int root = order[first + item];
         const RootInfo R = decode_root(boards[root]);
         if (use_global)
-            solve_root<256>(R, T, mine, mine + 4 * kDagGlobalLayer, lds, out + 4 * (size_t)root,
+            solve_root<256>(R, T, mine, mine + 4 * kDagGlobalLayer, kDagGlobalLayer, lds, out + 4 * (size_t)root,
                             s_slots[0], s_slots[1]);
         else
-            solve_root<256>(R, T, lds, lds + 4 * T.dag_max[R.e], lds + 8 * T.dag_max[R.e],
+            solve_root<256>(R, T, lds, lds + 4 * T.dag_max[R.e], T.dag_max[R.e], lds + 8 * T.dag_max[R.e],
                             out + 4 * (size_t)root, s_slots[0], s_slots[1]);
         __syncthreads();
     }
@@ -536,7 +603,7 @@ hipError_t launch_eval_persistent(const uint64_t *boards, size_t n, uint4 *out,
 }
 
 // Workgroup size of the persistent classes 0 and 1 (256 or 512 threads per
-// root; class 2 takes a wave per root in 256-thread workgroups).
+// root; class 2 solves roots by waves in 256-thread workgroups).
 static int g_class_threads[2] = {512, 256};
 
 void set_eval_class_threads(int c0, int c1)
