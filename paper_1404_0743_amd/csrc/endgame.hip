@@ -260,10 +260,14 @@ __device__ void solve_root(const RootInfo &R, const DevTables &T, uint4 *buf0, u
     }
 }
 
-// Count roots per number of empty cells (index 11: invalid boards).  Counts
-// are gathered per workgroup in LDS first, so each workgroup adds to the
-// global counters once per bin (a million lanes adding to twelve global
-// counters directly serialise on them).
+// Binning: each thread takes kBinPer boards (a workgroup 256 * kBinPer
+// consecutive ones, coalesced per round), so that a workgroup's counts, kept
+// in LDS, go to the global counters once per bin for that many boards: the
+// global counters are twelve addresses, and every workgroup's atomics on
+// them serialise.
+constexpr int kBinPer = 8;
+
+// Count roots per number of empty cells (index 11: invalid boards).
 __global__ void __launch_bounds__(256)
     eval_count_kernel(const uint64_t *boards, size_t n, int *count, uint8_t *empties, int *status,
                       uint4 *out)
@@ -271,8 +275,9 @@ __global__ void __launch_bounds__(256)
     __shared__ int lc[12];
     if (threadIdx.x < 12) lc[threadIdx.x] = 0;
     __syncthreads();
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
+    for (int r = 0; r < kBinPer; r++) {
+        const size_t i = ((size_t)blockIdx.x * kBinPer + r) * 256 + threadIdx.x;
+        if (i >= n) break;
         const RootInfo R = decode_root(boards[i]);
         const int e = R.valid ? R.e : 11;
         empties[i] = (uint8_t)e;
@@ -311,13 +316,21 @@ __global__ void __launch_bounds__(256)
     __shared__ int lc[11], base[11];
     if (threadIdx.x < 11) lc[threadIdx.x] = 0;
     __syncthreads();
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int e = i < n ? empties[i] : 11;
-    const int local = e <= 10 ? atomicAdd(&lc[e], 1) : 0;
+    int ee[kBinPer], local[kBinPer];
+#pragma unroll
+    for (int r = 0; r < kBinPer; r++) {
+        const size_t i = ((size_t)blockIdx.x * kBinPer + r) * 256 + threadIdx.x;
+        ee[r] = i < n ? empties[i] : 11;
+        local[r] = ee[r] <= 10 ? atomicAdd(&lc[ee[r]], 1) : 0;
+    }
     __syncthreads();
     if (threadIdx.x < 11 && lc[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], lc[threadIdx.x]);
     __syncthreads();
-    if (e <= 10) order[start[e] + base[e] + local] = (int)i;
+#pragma unroll
+    for (int r = 0; r < kBinPer; r++) {
+        const size_t i = ((size_t)blockIdx.x * kBinPer + r) * 256 + threadIdx.x;
+        if (ee[r] <= 10) order[start[ee[r]] + base[ee[r]] + local[r]] = (int)i;
+    }
 }
 
 __global__ void zero_ints_kernel(int *p, int n)
@@ -335,9 +348,9 @@ __global__ void zero_ints_kernel(int *p, int n)
 //            first, then join the others on the 8-empty queue);
 //   class 1: 7 empty cells, a workgroup per root, a smaller LDS footprint;
 //   class 2: up to kWaveMaxEmpties, synchronised per wave only: a wave
-//            solves four roots with up to 4 empty cells at once (16 lanes
-//            each), two with 5 (32 lanes), one with 6, each on its own part
-//            of the wave's LDS.
+//            solves eight roots with up to 3 empty cells at once (8 lanes
+//            each), four with 4 (16 lanes), two with 5 (32 lanes) or one
+//            with 6, each on its own part of the wave's LDS.
 constexpr int kWaveMaxEmpties = 6;
 // two layers of the widest 6-empty layer, then the five-set tables (C(6,3) = 20)
 constexpr int kWaveLdsBytes = 2 * 90 * 64 + 2 * 20 * 32;
@@ -386,13 +399,13 @@ __global__ void __launch_bounds__(NT)
             __syncthreads();
         }
     } else {
-        // A wave takes a chunk of K roots of one bin (K = 4 up to 4 empty
-        // cells, 2 for 5, 1 for 6: the widest layers have 12, 30 and 90
-        // nodes); the roots of a chunk have the same layers, so the wave
+        // A wave takes a chunk of K roots of one bin (K = 8 up to 3 empty
+        // cells, 4 for 4, 2 for 5, 1 for 6: the widest layers have 6, 12, 30
+        // and 90 nodes); the roots of a chunk have the same layers, so the wave
         // synchronises them together.  Chunks are numbered bin by bin, most
         // empty cells first; the last chunk of a bin repeats the bin's last
         // root where it runs short (the copy writes the same bytes).
-        __shared__ int s_sub[4][4][2][10];
+        __shared__ int s_sub[4][8][2][kWaveMaxEmpties];
         (void)lo;
         (void)hi;
         const int w = threadIdx.x >> 6, wl = threadIdx.x & 63;
@@ -405,7 +418,7 @@ __global__ void __launch_bounds__(NT)
             long long cum = 0;
             for (int b = kWaveMaxEmpties; b >= 0; b--) {
                 const int blo = start[b], bhi = b == 0 ? start[11] : start[b - 1];
-                const int kb = b <= 4 ? 4 : b == 5 ? 2 : 1;
+                const int kb = b <= 3 ? 8 : b == 4 ? 4 : b == 5 ? 2 : 1;
                 const long long nch = (bhi - blo + kb - 1) / kb;
                 if (e < 0 && c < cum + nch) {
                     e = b;
@@ -420,7 +433,10 @@ __global__ void __launch_bounds__(NT)
             const int root = order[min(base + g, last)];
             const RootInfo R = decode_root(boards[root]);
             uint4 *o = out + 4 * (size_t)root;
-            if (K == 4) {
+            if (K == 8) {
+                uint4 *sb = wb + g * 100;   // 1.6 KB each: layers of 6 nodes, tables of 3 subsets
+                solve_root<8>(R, T, sb, sb + 4 * 6, 6, sb + 8 * 6, o, s_sub[w][g][0], s_sub[w][g][1]);
+            } else if (K == 4) {
                 uint4 *sb = wb + g * 200;   // 3.2 KB each: layers of 12 nodes, tables of 6 subsets
                 solve_root<16>(R, T, sb, sb + 4 * 12, 12, sb + 8 * 12, o, s_sub[w][g][0], s_sub[w][g][1]);
             } else if (K == 2) {
@@ -567,13 +583,13 @@ hipError_t launch_eval_bin(const uint64_t *boards, size_t n, const EvalScratch &
     (void)T;
     hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, S.count, 16);
     if (n) {
-        const unsigned g = (unsigned)((n + 255) / 256);
+        const unsigned g = (unsigned)((n + 256 * kBinPer - 1) / (256 * kBinPer));
         hipLaunchKernelGGL(eval_count_kernel, dim3(g), dim3(256), 0, s, boards, n, S.count,
                            S.empties, status, out);
     }
     hipLaunchKernelGGL(eval_scan_kernel, dim3(1), dim3(64), 0, s, S.count, S.start, S.cursor);
     if (n) {
-        const unsigned g = (unsigned)((n + 255) / 256);
+        const unsigned g = (unsigned)((n + 256 * kBinPer - 1) / (256 * kBinPer));
         hipLaunchKernelGGL(eval_scatter_kernel, dim3(g), dim3(256), 0, s, S.empties, n, S.start,
                            S.cursor, S.order);
     }
