@@ -1,7 +1,8 @@
 """GPU parity of the endgame solver (pentago_eval_batch, the Section VIII
 serial solver run per board on the device) against O2 (minimax over the
 Section II rules), bit for bit.  Covers 0..10 empty cells (the LDS and the
-global layer paths), boards that already show fives, invalid boards, the
+global layer paths, the roots packed several to a wave and the short chunks
+at the end of a bin), boards that already show fives, invalid boards, the
 persistent and the grouped launch forms and their equality."""
 import sys
 
@@ -72,6 +73,26 @@ def test_mixed_empties_and_forms(P):
     pick = np.concatenate([rng.choice(len(boards), 300, replace=False), np.arange(len(boards), len(allb))])
     want = O.minimax_tables(allb[pick])
     assert np.array_equal(got[pick], want)
+
+
+@pytest.mark.parametrize("e", range(7))
+def test_packed_wave_chunks_and_tails(P, e):
+    """Roots with up to 6 empty cells are solved several to a wave (eight up
+    to 3 empty cells, four with 4, two with 5); a bin whose size is not a
+    multiple of the chunk ends in a short chunk that repeats its last root.
+    Batches of 1 to 9 and 17 roots with e empty cells leave every tail
+    length; each batch is checked against O2."""
+    stones = 36 - e
+    if e >= 3:
+        boards = I.random_play_boards(17, stones, stones, seed=60 + e)
+    else:
+        boards = I.random_placement_boards(17, (stones + 1) // 2, stones // 2, seed=60 + e)
+    log("packed chunks, empty cells", e)
+    want = O.minimax_tables(boards)
+    for n in (1, 2, 3, 4, 5, 6, 7, 8, 9, 17):
+        got, bad = gpu_eval(P, boards[:n])
+        assert bad == 0
+        assert np.array_equal(got, want[:n]), n
 
 
 def test_deep_roots_global_layers(P):
