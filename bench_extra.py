@@ -161,8 +161,8 @@ def layers(P, torch, stream, resident=None):
 
         med_plain, _ = _time(torch, stream, plain, 5)
         ref = [o.clone() for _, _, o in jobs]
-        # the batched sweep's tile LDS cap, tuned on this layer (set-up)
-        cap, _ = P.pentago_autotune_sections(jobs, stream=stream)
+        # the batched sweep's tile shape (threads, LDS cap), tuned on this layer (set-up)
+        cap, nt, _ = P.pentago_autotune_sections(jobs, stream=stream)
         plan = P.SweepPlan(jobs)
         med_graph, _ = _time(torch, stream, lambda: plan.launch(stream, graph=True), 5)
         same = all(torch.equal(r, o) for r, (_, _, o) in zip(ref, jobs))
@@ -177,7 +177,7 @@ def layers(P, torch, stream, resident=None):
             "plain_ms": med_plain, "plain_positions_per_s": positions / (med_plain * 1e-3),
             "batched_graph_ms": med_graph, "batched_positions_per_s": positions / (med_graph * 1e-3),
             "batched_over_plain": med_plain / med_graph, "same_bytes": same,
-            "tiles": info["tiles"], "grid": info["grid"], "tile_lds_cap": cap,
+            "tiles": info["tiles"], "grid": info["grid"], "tile_lds_cap": cap, "tile_threads": nt,
             "counts": table_counts(P, torch, [o for _, _, o in jobs], stream)}
         log("layer %d: plain %.3f ms, batched %.3f ms" % (stones, med_plain, med_graph))
     out["resident_child_bytes"] = sum(t.numel() * 8 for t in cache.values())
@@ -385,7 +385,7 @@ def slices(P, torch, stream):
         for counts, children, _ in jobs:
             reads += sum(c.shape[0] for c in children if c is not None)
         alg = 64 * entries + 64 * reads
-        cap, _ = P.pentago_autotune_sections(jobs, reps=True, stream=stream)   # set-up
+        cap, nt, _ = P.pentago_autotune_sections(jobs, reps=True, stream=stream)   # set-up
         t_batched, _ = _time(torch, stream, lambda: P.pentago_solve_sections_d4(jobs, stream), 5)
         keep = {k: v.clone() for k, v in sorted(tables.items(), key=lambda kv: -kv[1].shape[0])[:8]}
         w = torch.randint(-(1 << 62), 1 << 62, (8,), dtype=torch.int64, device="cuda")
@@ -410,7 +410,7 @@ def slices(P, torch, stream):
             "graph_positions_per_s": pos / (t_graph * 1e-3),
             "graph_positions_all_images_per_s": cover / (t_graph * 1e-3),
             "graph_algorithmic_GB_s": alg / (t_graph * 1e-3) / 1e9,
-            "graph_over_per_section": t_plain / t_graph, "same_bytes": bool(same), "tile_lds_cap": cap,
+            "graph_over_per_section": t_plain / t_graph, "same_bytes": bool(same), "tile_lds_cap": cap, "tile_threads": nt,
             "counts": table_counts(P, torch, tables.values(), stream)}
         del keep
         if stones == 34:

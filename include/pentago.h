@@ -219,15 +219,17 @@ typedef struct {
 int pentago_solve_sections(const pentago_section_job *jobs, size_t n, void *hip_stream);
 
 /* Autotuner of the batched sweep: times the jobs (as pentago_solve_sections,
- * or pentago_solve_sections_d4 when reps is nonzero) with each cap on a
- * tile's LDS bytes that the library supports (24, 32, 40 and 52 KiB: a tile
- * above the cap takes fewer lines), three timed launches each after a
- * warm-up, and keeps the fastest cap for every later batch of the same stone
- * count in this process (without tuning: 52 KiB).  The jobs' outputs hold
- * their results afterwards.  cap_bytes and best_ms (may be NULL) receive the
- * cap and its time.  Synchronises hip_stream. */
+ * or pentago_solve_sections_d4 when reps is nonzero) with each tile shape
+ * the library supports, 256 or 512 threads per tile times a cap on a tile's
+ * LDS bytes of 24, 32, 40 or 52 KiB (a tile above the cap takes fewer
+ * lines), three timed launches each after a warm-up, and keeps the fastest
+ * shape for every later batch of the same stone count in this process
+ * (without tuning: 512 threads, 52 KiB).  The jobs' outputs hold their
+ * results afterwards.  cap_bytes, threads and best_ms (each may be NULL)
+ * receive the cap, the thread count and their time.  Synchronises
+ * hip_stream. */
 int pentago_autotune_sections(const pentago_section_job *jobs, size_t n, int reps, void *hip_stream,
-                              int *cap_bytes, float *best_ms);
+                              int *cap_bytes, int *threads, float *best_ms);
 
 /* The same with every job's children held as their representatives under
  * the board symmetries (child[j] as rep[j] of pentago_solve_section_d4): the

@@ -20,6 +20,7 @@ struct pentago_sweep_plan {
     int njobs = 0, nunits = 0;
     long long total_tiles = 0, total_chunks = 0;
     int lds_bytes = 0;
+    int threads = 512;  // per tile workgroup
     // jobs [0, nbig) have tiles above the LDS cap even with one line;
     // they take a second launch, beside the first on a side stream
     int nbig = 0;
@@ -42,34 +43,42 @@ namespace pg {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// LDS bound of one batched tile (bytes) unless pentago_autotune_sections
-// has picked one for the layer's stone count: three workgroups per CU, the
-// headline tile shape (7 lines of 160 patterns) included.
-constexpr int kBatchLds = 53248;
-// Caps the autotuner tries (the kernel runs at most three 512-thread
-// workgroups per CU, so larger caps only cost occupancy).
+// Tile shape of a batch unless pentago_autotune_sections has picked one
+// for the layer's stone count: an LDS bound per tile of 52 KiB (three
+// workgroups per CU, the headline tile shape, 7 lines of 160 patterns,
+// included) and 512 threads per tile.
+struct BatchShape {
+    int cap, threads;
+};
+constexpr BatchShape kBatchDefault = {53248, 512};
+// Caps and workgroup sizes the autotuner tries (at most three 512-thread
+// workgroups run per CU, so larger caps only cost occupancy; 256 threads
+// suit layers of short lines, whose small tiles leave most of 512 threads
+// idle).
 constexpr int kBatchCaps[] = {24576, 32768, 40960, 53248};
+constexpr int kBatchThreadChoices[] = {256, 512};
 
-static std::mutex g_cap_mutex;
-static int g_cap[37];   // per stone count; 0: kBatchLds
+static std::mutex g_shape_mutex;
+static BatchShape g_shape[37];   // per stone count; cap 0: kBatchDefault
 
-static int batch_cap(int stones)
+static BatchShape batch_shape(int stones)
 {
-    std::lock_guard<std::mutex> lock(g_cap_mutex);
-    const int c = stones >= 0 && stones <= 36 ? g_cap[stones] : 0;
-    return c > 0 ? c : kBatchLds;
+    std::lock_guard<std::mutex> lock(g_shape_mutex);
+    const BatchShape b = stones >= 0 && stones <= 36 ? g_shape[stones] : BatchShape{0, 0};
+    return b.cap > 0 ? b : kBatchDefault;
 }
 
 // Build a plan: job table in decreasing order of work, prep units for the
 // dimensions that are not staged, and the device block holding all of it.
 // With `stream` the device block is allocated stream-ordered on it.
 static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t stream, bool async,
-                      bool reps, pentago_sweep_plan **out, int cap = 0)
+                      bool reps, pentago_sweep_plan **out, BatchShape shape = {0, 0})
 {
     if (!jobs || n == 0) return fail(PENTAGO_EINVAL, "no jobs");
     if (n > 65536) return fail(PENTAGO_ERANGE, "more than 65536 jobs");
     const int stones = section_stones(jobs[0].section);
-    const int lds_cap = cap > 0 ? cap : batch_cap(stones);
+    if (shape.cap <= 0) shape = batch_shape(stones);
+    const int lds_cap = shape.cap;
     std::vector<SweepJob> J(n);
     for (size_t i = 0; i < n; i++) {
         if (section_stones(jobs[i].section) != stones)
@@ -167,6 +176,7 @@ static int plan_build(const pentago_section_job *jobs, size_t n, hipStream_t str
     P->total_tiles = tiles;
     P->total_chunks = chunks;
     P->lds_bytes = lds;
+    P->threads = shape.threads;
     P->nbig = nbig;
     P->tiles_big = tiles_big;
     P->lds_big = lds_big;
@@ -239,10 +249,11 @@ static int plan_enqueue(pentago_sweep_plan *P, hipStream_t st)
     }
     // the large-LDS tiles on the caller's stream, the others beside them
     if (e == hipSuccess && P->tiles_big > 0)
-        e = launch_sweep_batch(P->d_jobs, P->d_tile_start, P->nbig, P->tiles_big, P->lds_big, P->sym, P->T, st);
+        e = launch_sweep_batch(P->d_jobs, P->d_tile_start, P->nbig, P->tiles_big, P->lds_big, P->threads, P->sym,
+                               P->T, st);
     if (e == hipSuccess && P->total_tiles > 0)
         e = launch_sweep_batch(P->d_jobs + P->nbig, P->d_tile_start + P->nbig, P->njobs - P->nbig,
-                               P->total_tiles, P->lds_bytes, P->sym, P->T, both ? side : st);
+                               P->total_tiles, P->lds_bytes, P->threads, P->sym, P->T, both ? side : st);
     if (e == hipSuccess && both) {
         e = hipEventRecord(join, side);
         if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);
@@ -339,48 +350,54 @@ int pentago_solve_sections_d4(const pentago_section_job *jobs, size_t n, void *h
 }
 
 int pentago_autotune_sections(const pentago_section_job *jobs, size_t n, int reps, void *hip_stream,
-                              int *cap_bytes, float *best_ms)
+                              int *cap_bytes, int *threads, float *best_ms)
 {
     if (!jobs || n == 0) return fail(PENTAGO_EINVAL, "no jobs");
     const hipStream_t st = (hipStream_t)hip_stream;
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
         return fail(PENTAGO_EDEVICE, "hipEventCreate");
-    int best_cap = 0, rc = 0;
+    BatchShape best_shape = kBatchDefault;
+    int rc = 0;
     float best = 1e30f;
-    for (int cap : kBatchCaps) {
-        pentago_sweep_plan *P = nullptr;
-        rc = plan_build(jobs, n, st, true, reps != 0, &P, cap);
-        if (rc) break;
-        rc = plan_enqueue(P, st);  // warm-up
-        float t = 1e30f;
-        for (int r = 0; r < 3 && rc == 0; r++) {
-            (void)hipEventRecord(a, st);
-            rc = plan_enqueue(P, st);
-            (void)hipEventRecord(b, st);
-            if (rc == 0 && hipEventSynchronize(b) != hipSuccess) rc = fail(PENTAGO_EDEVICE, "hipEventSynchronize");
-            float ms = 0;
-            if (rc == 0) (void)hipEventElapsedTime(&ms, a, b);
-            t = std::min(t, ms);
+    for (int nt : kBatchThreadChoices) {
+        for (int cap : kBatchCaps) {
+            const BatchShape shape = {cap, nt};
+            pentago_sweep_plan *P = nullptr;
+            rc = plan_build(jobs, n, st, true, reps != 0, &P, shape);
+            if (rc) break;
+            rc = plan_enqueue(P, st);  // warm-up
+            float t = 1e30f;
+            for (int r = 0; r < 3 && rc == 0; r++) {
+                (void)hipEventRecord(a, st);
+                rc = plan_enqueue(P, st);
+                (void)hipEventRecord(b, st);
+                if (rc == 0 && hipEventSynchronize(b) != hipSuccess) rc = fail(PENTAGO_EDEVICE, "hipEventSynchronize");
+                float ms = 0;
+                if (rc == 0) (void)hipEventElapsedTime(&ms, a, b);
+                t = std::min(t, ms);
+            }
+            (void)hipFreeAsync(P->dev, st);
+            (void)hipStreamSynchronize(st);
+            delete P;
+            if (rc) break;
+            if (t < best) {
+                best = t;
+                best_shape = shape;
+            }
         }
-        (void)hipFreeAsync(P->dev, st);
-        (void)hipStreamSynchronize(st);
-        delete P;
         if (rc) break;
-        if (t < best) {
-            best = t;
-            best_cap = cap;
-        }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (rc) return rc;
     const int stones = section_stones(jobs[0].section);
     {
-        std::lock_guard<std::mutex> lock(g_cap_mutex);
-        if (stones >= 0 && stones <= 36) g_cap[stones] = best_cap;
+        std::lock_guard<std::mutex> lock(g_shape_mutex);
+        if (stones >= 0 && stones <= 36) g_shape[stones] = best_shape;
     }
-    if (cap_bytes) *cap_bytes = best_cap;
+    if (cap_bytes) *cap_bytes = best_shape.cap;
+    if (threads) *threads = best_shape.threads;
     if (best_ms) *best_ms = best;
     return 0;
 }

@@ -96,13 +96,12 @@ hipError_t launch_prep(const SweepJob &job, int j, const DevTables &T, hipStream
 hipError_t launch_prep_batch(const SweepJob *dev_jobs, const int *dev_unit,
                              const long long *dev_chunk_start, int nunits, long long total_chunks,
                              const DevTables &T, hipStream_t s);
-// Threads per workgroup of the batched sweep.
-constexpr int kBatchThreads = 512;
-// One workgroup per tile of jobs [0, njobs) (tile_start: first global tile
-// of each job).  sym: jobs whose children may be held as their
-// representatives (csym).
+// One workgroup of `threads` (256 or 512) per tile of jobs [0, njobs)
+// (tile_start: first global tile of each job).  sym: jobs whose children may
+// be held as their representatives (csym).
 hipError_t launch_sweep_batch(const SweepJob *dev_jobs, const long long *dev_tile_start, int njobs,
-                              long long total_tiles, int lds_bytes, bool sym, const DevTables &T, hipStream_t s);
+                              long long total_tiles, int lds_bytes, int threads, bool sym, const DevTables &T,
+                              hipStream_t s);
 
 // Endgame (Section VIII serial solver, one DAG per root).
 struct EvalScratch {

@@ -685,17 +685,21 @@ __device__ __forceinline__ void sweep_batch_tile(const SweepJob *jobs, const lon
     }
 }
 
-// 512 threads, at least 6 (5 with the symmetry variants) waves per SIMD:
-// three workgroups of tiles up to 52 KiB of LDS per CU, as the tuned
-// single-section sweep
-__global__ void __launch_bounds__(512, 6)
+// NT = 256 or 512 threads per tile (the batch autotuner picks one per
+// layer), at least 6 (5 with the symmetry variants) waves per SIMD: three
+// 512-thread workgroups of tiles up to 52 KiB of LDS per CU, as the tuned
+// single-section sweep, or twice as many 256-thread ones where the tiles
+// are small (short lines leave most of 512 threads idle in every phase)
+template <int NT>
+__global__ void __launch_bounds__(NT, 6)
     sweep_batch_kernel(const SweepJob *jobs, const long long *tile_start, int njobs, long long total, DevTables T)
 {
     sweep_batch_tile<false>(jobs, tile_start, njobs, total, T);
 }
 
 // The same over jobs whose children may be held as their representatives.
-__global__ void __launch_bounds__(512, 5)
+template <int NT>
+__global__ void __launch_bounds__(NT, 5)
     sweep_batch_sym_kernel(const SweepJob *jobs, const long long *tile_start, int njobs, long long total,
                            DevTables T)
 {
@@ -776,16 +780,23 @@ hipError_t launch_prep_batch(const SweepJob *dev_jobs, const int *dev_unit,
 }
 
 hipError_t launch_sweep_batch(const SweepJob *dev_jobs, const long long *dev_tile_start, int njobs,
-                              long long total_tiles, int lds_bytes, bool sym, const DevTables &T, hipStream_t s)
+                              long long total_tiles, int lds_bytes, int threads, bool sym, const DevTables &T,
+                              hipStream_t s)
 {
     if (total_tiles <= 0) return hipSuccess;
-    if (total_tiles > 0x7fffffffLL) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)total_tiles), block(kBatchThreads);
-    if (sym)
-        hipLaunchKernelGGL(sweep_batch_sym_kernel, grid, block, lds_bytes, s, dev_jobs, dev_tile_start, njobs,
+    if (total_tiles > 0x7fffffffLL || (threads != 256 && threads != 512)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)total_tiles), block(threads);
+    if (sym && threads == 512)
+        hipLaunchKernelGGL(sweep_batch_sym_kernel<512>, grid, block, lds_bytes, s, dev_jobs, dev_tile_start, njobs,
+                           total_tiles, T);
+    else if (sym)
+        hipLaunchKernelGGL(sweep_batch_sym_kernel<256>, grid, block, lds_bytes, s, dev_jobs, dev_tile_start, njobs,
+                           total_tiles, T);
+    else if (threads == 512)
+        hipLaunchKernelGGL(sweep_batch_kernel<512>, grid, block, lds_bytes, s, dev_jobs, dev_tile_start, njobs,
                            total_tiles, T);
     else
-        hipLaunchKernelGGL(sweep_batch_kernel, grid, block, lds_bytes, s, dev_jobs, dev_tile_start, njobs,
+        hipLaunchKernelGGL(sweep_batch_kernel<256>, grid, block, lds_bytes, s, dev_jobs, dev_tile_start, njobs,
                            total_tiles, T);
     return hipGetLastError();
 }

@@ -88,7 +88,7 @@ _SIGS = {
     "pentago_init": ([], ctypes.c_int),
     "pentago_autotune_eval": ([_P, ctypes.c_size_t, _P, _P, _P, _P], ctypes.c_int),
     "pentago_table_counts": ([_P, ctypes.c_uint64, _P, _P], ctypes.c_int),
-    "pentago_autotune_sections": ([_P, ctypes.c_size_t, ctypes.c_int, _P, _P, _P], ctypes.c_int),
+    "pentago_autotune_sections": ([_P, ctypes.c_size_t, ctypes.c_int, _P, _P, _P, _P], ctypes.c_int),
     "pentago_validate_table": ([_P, ctypes.c_uint64, _P], ctypes.c_int),
     "pentago_set_validate": ([ctypes.c_int], ctypes.c_int),
     "pentago_eval_batch_noalloc": ([_P, ctypes.c_size_t, _P, _P, _P], ctypes.c_int),
@@ -304,13 +304,14 @@ def pentago_solve_sections(jobs, stream=None):
 
 
 def pentago_autotune_sections(jobs, reps=False, stream=None):
-    """Time the batched sweep's tile LDS caps on these jobs, keep the fastest
-    for their stone count; returns (cap in bytes, best ms)."""
+    """Time the batched sweep's tile shapes (threads per tile, tile LDS cap)
+    on these jobs, keep the fastest for their stone count; returns (cap in
+    bytes, threads, best ms)."""
     arr = _job_array(jobs)
-    cap, ms = ctypes.c_int(), ctypes.c_float()
+    cap, nt, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
     _check(lib().pentago_autotune_sections(arr, len(jobs), 1 if reps else 0, _stream(stream), ctypes.byref(cap),
-                                           ctypes.byref(ms)), "pentago_autotune_sections")
-    return cap.value, ms.value
+                                           ctypes.byref(nt), ctypes.byref(ms)), "pentago_autotune_sections")
+    return cap.value, nt.value, ms.value
 
 
 def pentago_solve_sections_d4(jobs, stream=None):

@@ -118,14 +118,15 @@ def test_autotuned_tiles_give_same_bytes(P):
 
 
 @pytest.mark.parametrize("stones", [34, 33])
-def test_autotuned_batch_cap_gives_same_bytes(P, stones):
-    """The batched sweep's LDS-cap autotuner leaves the jobs' results in
-    their outputs, and later batches of that stone count (which take the
-    tuned cap) give the same bytes as the per-section sweep."""
+def test_autotuned_batch_shape_gives_same_bytes(P, stones):
+    """The batched sweep's tile-shape autotuner (threads per tile, LDS cap)
+    leaves the jobs' results in their outputs, and later batches of that
+    stone count (which take the tuned shape) give the same bytes as the
+    per-section sweep."""
     log("batch autotune", stones)
     secs, plain, jobs = layer(P, stones, 16, seed=700 + stones)
-    cap, ms = P.pentago_autotune_sections(jobs)
-    assert cap in (24576, 32768, 40960, 53248) and ms > 0
+    cap, threads, ms = P.pentago_autotune_sections(jobs)
+    assert cap in (24576, 32768, 40960, 53248) and threads in (256, 512) and ms > 0
     torch.cuda.synchronize()
     for s, ref, (_, _, out) in zip(secs, plain, jobs):
         assert torch.equal(ref, out), s
