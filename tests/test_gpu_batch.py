@@ -117,7 +117,7 @@ def test_autotuned_tiles_give_same_bytes(P):
     assert torch.equal(ref, out2)
 
 
-@pytest.mark.parametrize("stones", [34, 33])
+@pytest.mark.parametrize("stones", [35, 34, 33])
 def test_autotuned_batch_shape_gives_same_bytes(P, stones):
     """The batched sweep's tile-shape autotuner (threads per tile, LDS cap)
     leaves the jobs' results in their outputs, and later batches of that
