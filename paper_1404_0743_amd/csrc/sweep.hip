@@ -630,8 +630,12 @@ __device__ __forceinline__ void sweep_tile(const SweepJob &J, const DevTables &T
     }
 }
 
+// 512 threads: at most 64 VGPRs (8 waves per SIMD, no scratch), so that four
+// workgroups of tiles up to 40 KiB of LDS share a CU (the tile autotuner
+// then takes 5 lines of 160 patterns for the headline section, against 7 at
+// three workgroups per CU); the symmetry variant needs more registers.
 template <int D, int NT, bool SYMC = false>
-__global__ void __launch_bounds__(NT, NT == 512 ? (SYMC ? 5 : 6) : 1) sweep_kernel(SweepJob J, DevTables T)
+__global__ void __launch_bounds__(NT, NT == 512 ? (SYMC ? 5 : 8) : 1) sweep_kernel(SweepJob J, DevTables T)
 {
     extern __shared__ uint4 lds[];
     uint32_t tile = blockIdx.x;
