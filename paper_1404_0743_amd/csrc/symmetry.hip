@@ -283,6 +283,22 @@ int pentago_solve_section_d4(pentago_section s, const pentago_superinfo *const r
     rc = make_job(s, rep, out, &J, -1, 0);
     if (rc) return rc;
     set_child_syms(s, rep, &J);
+    // the staged child read through a symmetry takes the kernel variant that
+    // needs more registers (two 512-thread workgroups per CU), so the tile
+    // shape tuned for the plain sweep, sized for four per CU, leaves LDS
+    // unused: take 7 lines (measured on the headline geometry: 148 us
+    // against 179 with the plain sweep's 5; 8 lines gave 176)
+    if (J.csym[J.d] && ((J.emask >> J.d) & 1) && !((J.odmask >> J.d) & 1) && J.threads == 512) {
+        const int cmd = J.cm[J.d];
+        int G = 7;
+        while (G > J.G && sweep_lds_bytes(G, J.m[J.d], cmd) > 65536) G--;
+        if (G > J.G) {
+            const int order = J.order;
+            rc = make_job(s, rep, out, &J, J.d, G, 512, order);
+            if (rc) return rc;
+            set_child_syms(s, rep, &J);
+        }
+    }
     rc = validate_children(J, (hipStream_t)hip_stream);
     if (rc) return rc;
     return run_job(J, T, (hipStream_t)hip_stream);
