@@ -180,3 +180,25 @@ def test_d4_sweep_full_size(P):
     assert torch.equal(got, direct)
     ondemand = gpu_solve(P, counts, [None] * 4)
     assert torch.equal(got, ondemand)
+
+
+def test_d4_sweep_with_tuned_shape(P):
+    """Once the tile autotuner has tuned the plain sweep of the headline
+    section, later sweeps of its geometry take the tuned shape; the sweep
+    over the child's representative, whose kernel variant takes more lines
+    per tile than that shape at 512 threads, still equals the plain sweep
+    bit for bit."""
+    counts = ((5, 4), (4, 5), (5, 4), (4, 4))
+    child = O.child_counts(counts, 3)
+    rep, sym = P.pentago_section_standardize(child)
+    assert sym != 0
+    n = O.section_entries(counts)
+    ct = gpu_solve(P, child, [None] * 4)
+    rep_t = gpu_solve(P, rep, [None] * 4)
+    plain = torch.empty((n, 8), dtype=torch.int64, device="cuda")
+    shape, _ = P.pentago_autotune_section(counts, [None, None, None, ct], plain)
+    log("tuned shape", shape)
+    got = torch.full_like(plain, -1)
+    P.pentago_solve_section_d4(counts, [None, None, None, rep_t], got)
+    torch.cuda.synchronize()
+    assert torch.equal(got, plain)
